@@ -1,0 +1,236 @@
+"""Seeded synthetic workloads: lattice geometry, initial signed-distance
+fields, parameter presets and sweep case tables.
+
+Both the FP64 oracle and the GPU library take their inputs from here.  The
+module holds no arithmetic of the lattice Boltzmann method itself: it builds
+wall masks, signed distances to the ink region and parameter tables, and each
+side turns them into distributions on its own.
+
+Geometry follows the paper's simulation set-up (Results, "Reproducing the
+experiment"): periodic left/right, a nozzle channel at the bottom opening into
+an ambient chamber, open ("fully developed") bottom and top rows, wetting
+walls.  The validation lattice of the paper (800 x 200, nozzle 120 high, radius
+40) is replaced by the synthetic configurations below, which keep its
+structure.
+"""
+from __future__ import annotations
+
+import math
+from typing import Iterable, List, Sequence, Tuple
+
+import numpy as np
+
+FLUID, WALL_INNER, WALL_OUTER = 0, 1, 2
+BC_PERIODIC, BC_OPEN = 0, 1
+
+MASK64 = (1 << 64) - 1
+
+
+# ------------------------------------------------------------------ RNG
+class SplitMix64:
+    """SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): counter-based 64-bit
+    generator, used for every seeded draw so that the sequence is fixed by
+    its published definition rather than by a library version."""
+
+    def __init__(self, seed: int):
+        self.state = seed & MASK64
+
+    def next_u64(self) -> int:
+        self.state = (self.state + 0x9E3779B97F4A7C15) & MASK64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+        return z ^ (z >> 31)
+
+    def uniform(self, lo: float = 0.0, hi: float = 1.0) -> float:
+        return lo + (hi - lo) * ((self.next_u64() >> 11) * (1.0 / (1 << 53)))
+
+    def randint(self, lo: int, hi: int) -> int:
+        """Uniform integer in [lo, hi] (inclusive)."""
+        return lo + int(self.uniform() * (hi - lo + 1)) if hi > lo else lo
+
+
+# ------------------------------------------------------------- geometry
+def nozzle_wall(nx: int, ny: int, x0: int, w: int, length: int) -> np.ndarray:
+    """Solid band y < length except the channel x0 <= x < x0 + w.  The two
+    columns that line the channel are the inner wall (class 1, the nozzle
+    inner wall whose contact angle the paper varies); the rest of the band,
+    including its top face, is the outer plate (class 2)."""
+    wall = np.zeros((ny, nx), dtype=np.uint8)
+    if w <= 0 or length <= 0:
+        return wall
+    wall[:length, :] = WALL_OUTER
+    wall[:length, x0:x0 + w] = FLUID
+    wall[:length, (x0 - 1) % nx] = WALL_INNER
+    wall[:length, (x0 + w) % nx] = WALL_INNER
+    return wall
+
+
+def channel_wall(nx: int, ny: int, x0: int, w: int) -> np.ndarray:
+    """Full-height vertical channel x0 <= x < x0 + w between inner walls."""
+    wall = np.full((ny, nx), WALL_INNER, dtype=np.uint8)
+    wall[:, x0:x0 + w] = FLUID
+    return wall
+
+
+def flat_wall(nx: int, ny: int, rows: Iterable[int] = (0,), cls: int = WALL_INNER) -> np.ndarray:
+    wall = np.zeros((ny, nx), dtype=np.uint8)
+    for r in rows:
+        wall[r, :] = cls
+    return wall
+
+
+# ------------------------------------------------------ signed distances
+def meniscus_distance(nx: int, ny: int, length: int) -> np.ndarray:
+    """Ink fills the rows below the nozzle exit: flat meniscus half a node
+    above the last nozzle row.  Positive inside the ink."""
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    return np.broadcast_to(length - 0.5 - y, (ny, nx)).copy()
+
+
+def discs_distance(nx: int, ny: int, discs: Sequence[Tuple[float, float, float]],
+                   periodic: bool = True, far: float = -1.0e3) -> np.ndarray:
+    """Signed distance to a union of discs (max over discs of R - |x - c|),
+    evaluated within a margin of each disc; `far` elsewhere."""
+    d = np.full((ny, nx), far, dtype=np.float64)
+    margin = 24.0
+    for (cx, cy, r) in discs:
+        ext = int(math.ceil(r + margin))
+        xs = np.arange(int(math.floor(cx)) - ext, int(math.floor(cx)) + ext + 2)
+        ys = np.arange(int(math.floor(cy)) - ext, int(math.floor(cy)) + ext + 2)
+        if periodic:
+            xi, yi = xs % nx, ys % ny
+        else:
+            kx = (xs >= 0) & (xs < nx)
+            ky = (ys >= 0) & (ys < ny)
+            xs, ys = xs[kx], ys[ky]
+            xi, yi = xs, ys
+        dist = np.sqrt((xs[None, :] - cx) ** 2 + (ys[:, None] - cy) ** 2)
+        sub = d[np.ix_(yi, xi)]
+        d[np.ix_(yi, xi)] = np.maximum(sub, r - dist)
+    return d
+
+
+def sample_discs(nx: int, ny: int, seed: int = 0, rmin: float = 8.0, rmax: float = 64.0,
+                 gap: float = 4.0, area_frac: float = 0.25, y_lo: float = 1.0,
+                 max_tries: int = 2_000_000) -> List[Tuple[float, float, float]]:
+    """Non-overlapping discs (clearance >= gap, periodic in x and y) with radii
+    uniform in [rmin, rmax] and uniform centres, drawn by rejection until the
+    ink area fraction reaches area_frac.  Discs stay at least `gap` away from
+    the rows y < y_lo (a flat wall there and its periodic image)."""
+    rng = SplitMix64(seed)
+    cx = np.zeros(0)
+    cy = np.zeros(0)
+    rr = np.zeros(0)
+    area = 0.0
+    target = area_frac * nx * ny
+    tries = 0
+    while area < target and tries < max_tries:
+        tries += 1
+        r = rng.uniform(rmin, rmax)
+        x = rng.uniform(0.0, nx)
+        y = rng.uniform(y_lo + gap + r, ny - gap - r)
+        if y_lo + gap + r >= ny - gap - r:
+            continue
+        if len(rr):
+            dx = np.abs(cx - x)
+            dx = np.minimum(dx, nx - dx)
+            dy = np.abs(cy - y)
+            dy = np.minimum(dy, ny - dy)
+            if np.any(np.sqrt(dx * dx + dy * dy) < rr + r + gap):
+                continue
+        cx = np.append(cx, x)
+        cy = np.append(cy, y)
+        rr = np.append(rr, r)
+        area += math.pi * r * r
+    return list(zip(cx.tolist(), cy.tolist(), rr.tolist()))
+
+
+# -------------------------------------------------------------- presets
+def base_params(nx: int, ny: int, **kw) -> dict:
+    p = dict(nx=nx, ny=ny, bc_y=BC_OPEN, force_rows=0, t_pos=0, t_neg=0, t_idle=0,
+             periodic_pulse=0, rho_ink=1.0, rho_amb=0.1, sigma=0.01, width=4.0, gamma=1.0,
+             tau_ink=1.0, tau_amb=1.0, tau_phi=1.0, theta_inner=90.0, theta_outer=90.0,
+             f_pos=0.0, f_neg=0.0)
+    p.update(kw)
+    return p
+
+
+def config_nozzle_small() -> dict:
+    """64 x 256 nozzle case (FP64 parity workload): channel 16 wide and 64
+    long, density 1.0/0.1, tau 1, contact angle 90 deg, pulse +1e-4 for 200
+    steps, -5e-5 for 100, then idle; 1000 steps."""
+    nx, ny, x0, w, L = 64, 256, 24, 16, 64
+    p = base_params(nx, ny, force_rows=L, t_pos=200, t_neg=100, t_idle=700,
+                    f_pos=1e-4, f_neg=5e-5)
+    return dict(name="nozzle_64x256", params=p, wall=nozzle_wall(nx, ny, x0, w, L),
+                distance=meniscus_distance(nx, ny, L), row0=L, steps=1000,
+                nozzle=(x0, w, L))
+
+
+def config_nozzle_single() -> dict:
+    """256 x 2048 single nozzle case: channel 32 wide and 256 long, contact
+    angle 60 deg, tau 0.8 ink / 1.0 ambient, pulse +2e-4 for 2000 steps,
+    -1e-4 for 1000, idle to 60000 steps."""
+    nx, ny, w, L = 256, 2048, 32, 256
+    x0 = (nx - w) // 2
+    p = base_params(nx, ny, force_rows=L, t_pos=2000, t_neg=1000, t_idle=57000,
+                    f_pos=2e-4, f_neg=1e-4, tau_ink=0.8, theta_inner=60.0)
+    return dict(name="nozzle_256x2048", params=p, wall=nozzle_wall(nx, ny, x0, w, L),
+                distance=None, row0=L, steps=60000, nozzle=(x0, w, L))
+
+
+def config_droplet_field(nx: int = 2048, ny: int = 16384, seed: int = 0,
+                         with_distance: bool = True) -> dict:
+    """Roofline stress: seeded disc field (radii 8-64, ink area >= 25 %),
+    periodic in x and y, one solid row y = 0 as a flat wetting wall at 120
+    deg, no driving force, tau 0.8 ink / 1.0 ambient, 5000 steps."""
+    p = base_params(nx, ny, bc_y=BC_PERIODIC, force_rows=ny, tau_ink=0.8,
+                    theta_inner=120.0, theta_outer=120.0)
+    cfg = dict(name=f"droplets_{nx}x{ny}", params=p, wall=flat_wall(nx, ny, (0,)), row0=1,
+               steps=5000, nozzle=None)
+    if with_distance:
+        discs = sample_discs(nx, ny, seed=seed, rmin=8.0, rmax=min(64.0, ny / 8, nx / 8),
+                             gap=p["width"], area_frac=0.25, y_lo=1.0)
+        cfg["discs"] = discs
+        cfg["distance"] = discs_distance(nx, ny, discs, periodic=True)
+    return cfg
+
+
+def sweep_cases(n: int = 256, seed: int = 1234, steps: int = 40000,
+                nx_range=(128, 384), ny_range=(1024, 3072), w_range=(12, 40),
+                theta_range=(30.0, 150.0), sigma_range=(0.005, 0.02),
+                f_range=(5e-5, 3e-4), t_range=(500, 3000), periodic_pulse=0) -> List[dict]:
+    """Seeded table of independent nozzle cases for a parameter sweep
+    (contact angle x surface tension x pulse, uneven lattice sizes)."""
+    rng = SplitMix64(seed)
+    out = []
+    for k in range(n):
+        nx = rng.randint(*nx_range)
+        ny = rng.randint(*ny_range)
+        w = rng.randint(*w_range)
+        theta = rng.uniform(*theta_range)
+        sigma = math.exp(rng.uniform(math.log(sigma_range[0]), math.log(sigma_range[1])))
+        fp = rng.uniform(*f_range)
+        fn = rng.uniform(*f_range)
+        tp = rng.randint(*t_range)
+        tn = rng.randint(*t_range)
+        ti = rng.randint(*t_range)
+        L = ny // 8
+        x0 = (nx - w) // 2
+        p = base_params(nx, ny, force_rows=L, t_pos=tp, t_neg=tn, t_idle=ti,
+                        periodic_pulse=periodic_pulse, f_pos=fp, f_neg=fn, tau_ink=0.8,
+                        theta_inner=theta, sigma=sigma)
+        out.append(dict(name=f"case{k}", params=p, nozzle=(x0, w, L), row0=L, steps=steps))
+    return out
+
+
+def case_wall(case: dict) -> np.ndarray:
+    p = case["params"]
+    x0, w, L = case["nozzle"]
+    return nozzle_wall(p["nx"], p["ny"], x0, w, L)
+
+
+def case_distance(case: dict) -> np.ndarray:
+    p = case["params"]
+    return meniscus_distance(p["nx"], p["ny"], case["nozzle"][2])
