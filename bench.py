@@ -1,0 +1,151 @@
+#!/usr/bin/env python3
+"""Throughput of the binary-fluid LBM hot path on one MI355X.
+
+Workload: the 2048 x 16384 droplet field (seeded discs, radii 8-64, ink area
+>= 25 %, flat wetting wall at 120 deg, tau 0.8 ink / 1.0 ambient).  One step
+is one fused collide-stream launch over the whole lattice; the droplet
+diagnostics (mass, momentum, per-row ink profile and segments) run every 50
+steps inside the timed region.  Prints one JSON line:
+
+  value      whole-job MLUPS = nx * ny * steps / timed seconds / 1e6
+  roofline   the fused kernel's algorithmic HBM bytes (14 float distributions
+             read and written per fluid node, 112 B) over its mean launch
+             time, against the 8 TB/s HBM peak
+  cpu_baseline  the FP64 oracle on a bounded slab of the same workload
+
+Usage: python bench.py [--gpus 1] [--steps 5000] [--warmup 100]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_NODE = 112  # 9 f + 5 g float32, read once and written once
+DIAG_EVERY = 50
+
+
+def cpu_baseline(cfg, rows: int = 4096, steps: int = 20) -> dict:
+    """FP64 oracle on a full-width band of the same disc field (rows
+    [0, rows), periodic), timed over `steps` steps after one warm-up step."""
+    from oracle import oracle as O
+    import workloads as W
+    import numpy as np
+    p = dict(cfg["params"], ny=rows)
+    wall = np.ascontiguousarray(cfg["wall"][:rows])
+    d = np.ascontiguousarray(cfg["distance"][:rows])
+    sim = O.OracleSim(p, wall)
+    sim.init_distance(d)
+    sim.step(1)
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    nodes = p["nx"] * rows
+    sim.close()
+    return {"value": round(nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": O.max_threads(),
+            "kind": "oracle",
+            "sample": f"{p['nx']}x{rows} band (rows 0-{rows - 1}) of the same disc field, periodic, "
+                      f"{steps} steps after 1 warm-up, FP64"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-steps", type=int, default=500,
+                    help="launches timed back-to-back for the fused kernel's mean duration")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the lattice update is measured on a single MI355X)", file=sys.stderr)
+        return 2
+
+    import torch
+    import workloads as W
+    from paper_1702_04487_amd import lbm
+
+    cfg = W.config_droplet_field()
+    p = dict(cfg["params"], diag_row0=cfg["row0"], diag_every=0)
+    nx, ny = p["nx"], p["ny"]
+    fluid_nodes = int((cfg["wall"] == 0).sum())
+    sim = lbm.Sim(p, cfg["wall"])
+    sim.init_distance(cfg["distance"])
+    stream = torch.cuda.current_stream()
+
+    def run(n):
+        done = 0
+        while done < n:
+            if (sim.t % DIAG_EVERY) == 0:
+                sim.diag_sample()
+            k = min(n - done, DIAG_EVERY - sim.t % DIAG_EVERY)
+            sim.step(k)
+            done += k
+
+    run(args.warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    run(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+
+    # mean duration of the fused collide-stream kernel alone: back-to-back
+    # launches on the same stream, no diagnostics in between
+    k0 = torch.cuda.Event(enable_timing=True)
+    k1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    k0.record(stream)
+    sim.step(args.kernel_steps)
+    k1.record(stream)
+    torch.cuda.synchronize()
+    kern_ms = k0.elapsed_time(k1) / args.kernel_steps
+
+    if sim.check() != lbm.IJ_OK:
+        print("bench.py: the run failed the stability guard", file=sys.stderr)
+        return 1
+    samples = sim.samples()
+    mass_drift = abs(samples[-1]["mass_n"] - samples[0]["mass_n"]) / abs(samples[0]["mass_n"])
+
+    achieved = BYTES_PER_NODE * fluid_nodes / (kern_ms * 1e-3) / 1e9
+    mlups = nx * ny * args.steps / (ms * 1e-3) / 1e6
+    out = {
+        "metric": "binary-LBM MLUPS + % HBM peak; sweep cases/hour plain vs batched+surrogate",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"droplet field {nx}x{ny} (seeded discs r 8-64, 25% ink, "
+                               f"wall 120 deg, periodic)",
+                   "nx": nx, "ny": ny, "diag_every": DIAG_EVERY, "tiling": "default"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_collide_fused", "kernel_ms": round(kern_ms, 5),
+                     "bytes_per_launch": BYTES_PER_NODE * fluid_nodes},
+        "mass_drift": mass_drift,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,217 @@
+/*
+ * inkjet_lbm.h -- C ABI of the MI355X (gfx950) binary-fluid lattice Boltzmann
+ * library for inkjet droplet formation.
+ *
+ * Method: He, Yang, Qin, Wen & Zhang, "The roles of wettability and surface
+ * tension in droplet formation during inkjet printing", arXiv:1702.04487.
+ *   - mean density n and order parameter phi (Methods, Eqs. 1 and 7);
+ *   - D2Q9 distributions f with BGK collision and the forcing of Eq. 4,
+ *     equilibrium Eqs. 5-6, streaming Eq. 3;
+ *   - D2Q5 distributions g with the modified streaming of Eq. 8 and the
+ *     equilibrium of Eqs. 9-10;
+ *   - the interfacial force mu_phi grad(phi) from neighbour gradients and the
+ *     pulsed +/-/idle body force of Results, "Actuation modeling" (Fig. 1);
+ *   - periodic left/right, "fully developed" top/bottom rows and wetting
+ *     walls with a set contact angle (Results, "Reproducing the experiment").
+ *
+ * Conventions shared by every entry point:
+ *   - Lattice x in [0,nx) (periodic), y in [0,ny) (jet direction).  Every
+ *     field array the caller passes or receives is row-major [ny][nx]
+ *     (index y*nx + x), float32 unless stated otherwise.
+ *   - Distribution arrays exchanged with the caller are [9][ny][nx] (f) and
+ *     [5][ny][nx] (g) with velocities c_0=(0,0) c_1=(1,0) c_2=(0,1)
+ *     c_3=(-1,0) c_4=(0,-1) c_5=(1,1) c_6=(-1,1) c_7=(-1,-1) c_8=(1,-1).
+ *   - "device" pointers are HIP device memory on the current device; "host"
+ *     pointers are ordinary process memory.  The library never frees memory
+ *     it did not allocate.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued on it and is asynchronous unless the entry
+ *     point says it synchronises.
+ *   - Every call returns an ij_status.  On failure the handle keeps a text
+ *     message (ij_last_error); no exception crosses the ABI.  A handle must
+ *     not be used from two threads at once.
+ */
+#ifndef INKJET_LBM_H
+#define INKJET_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IJ_OK = 0,
+    IJ_ERR_INVALID_ARG = -1, /* bad parameter, size or geometry; nothing changed */
+    IJ_ERR_OOM = -2,         /* device allocation failed */
+    IJ_ERR_DEVICE = -3,      /* a HIP call failed (message has the HIP error) */
+    IJ_ERR_UNSTABLE = -4,    /* a diagnostics sample saw NaN or |u| > u_limit */
+    IJ_ERR_STATE = -5        /* call out of order (e.g. step before init) */
+} ij_status;
+
+enum { IJ_BC_PERIODIC = 0, IJ_BC_OPEN = 1 };
+enum { IJ_FLUID = 0, IJ_WALL_INNER = 1, IJ_WALL_OUTER = 2 };
+
+/* Simulation parameters (all fields 8 bytes wide).  Lattice units. */
+typedef struct ij_params {
+    int64_t nx, ny;            /* lattice size, nx >= 3, ny >= 3 */
+    int64_t bc_y;              /* IJ_BC_PERIODIC or IJ_BC_OPEN ("fully developed"
+                                  top and bottom rows, Results) */
+    int64_t force_rows;        /* body force acts on fluid nodes with y < force_rows */
+    int64_t t_pos, t_neg, t_idle; /* pulse durations in steps (Fig. 1) */
+    int64_t periodic_pulse;    /* nonzero: repeat the pulse with period t_pos+t_neg+t_idle */
+    int64_t nozzle_x0, nozzle_w, nozzle_len; /* nozzle channel; nozzle_w = 0: none */
+    int64_t diag_row0;         /* first row of the droplet diagnostics (nozzle exit) */
+    int64_t diag_every;        /* ij_step samples diagnostics every K steps (0: never) */
+    double rho_ink, rho_amb;   /* bulk densities: phi* = (rho_ink-rho_amb)/2, n0 = mean */
+    double sigma, width;       /* surface tension and interface width W */
+    double gamma;              /* mobility parameter Gamma of Eq. 10 */
+    double tau_ink, tau_amb;   /* relaxation time of f in ink / ambient (Eq. 4) */
+    double tau_phi;            /* relaxation time of g (Eq. 8), q = 1/(tau_phi+1/2) */
+    double theta_inner, theta_outer; /* contact angles (degrees, through the ink) of
+                                        wall classes IJ_WALL_INNER / IJ_WALL_OUTER */
+    double f_pos, f_neg;       /* magnitudes of the positive / negative force pulses */
+    double u_limit;            /* stability guard on max |u| (<= 0: 0.3) */
+} ij_params;
+
+/* One diagnostics sample (Results: breakup time, drop velocity). */
+typedef struct ij_sample {
+    int64_t step;
+    double mass_n, mass_phi;   /* sum of n and of phi over fluid nodes */
+    double mom_x, mom_y;       /* sum over fluid nodes of sum_i c_i f_i */
+    double max_u;              /* max |u| over fluid nodes */
+    int64_t nan_count;         /* fluid nodes with a non-finite n, phi or u */
+    int64_t n_detached;        /* detached ink segments (rows >= diag_row0) */
+    int64_t largest_count;     /* ink nodes (phi > 0) of the largest one */
+    double largest_uy;         /* sum of u_y over those nodes */
+    int64_t largest_top;       /* its highest row (-1: none) */
+} ij_sample;
+
+/* Summary of the samples recorded so far. */
+typedef struct ij_diag {
+    int64_t step;              /* current time step */
+    int64_t n_samples;
+    int64_t breakup_step;      /* first sample with a detached drop, -1: none */
+    double v_drop;             /* mean drop velocity over [t_b+1000, t_b+3000] (NaN: none) */
+    int64_t vol_drop;          /* ink nodes of the drop at t_b+2000 */
+    int64_t satellite;         /* >= 2 detached drops at t_b+2000 */
+    int64_t unstable_step;     /* first sample failing the guard, -1: none */
+    ij_sample last;            /* the latest sample */
+} ij_diag;
+
+typedef struct ij_sim ij_sim;
+
+/* Fill *p with the 64x256 nozzle defaults (density 1.0/0.1, tau 1, theta 90,
+ * sigma 0.01, W 4, Gamma 1, no pulse). */
+ij_status ij_params_default(ij_params *p);
+
+/* Validate *p, derive the model constants (phi*, n0, beta, kappa, q, wetting
+ * offsets) and allocate device memory on the current device: two
+ * distribution buffers unless ij_attach_buffers follows, the wall mask
+ * (nozzle of nozzle_x0/w/len, or all fluid), scratch fields and the
+ * diagnostics ring.  *out receives the handle.  On failure *out is NULL and
+ * ij_last_error(NULL) describes the error. */
+ij_status ij_create(const ij_params *p, ij_sim **out);
+
+/* Release everything the library allocated.  NULL is allowed. */
+void ij_destroy(ij_sim *s);
+
+/* Text of the last error of the handle (or of the last failed create when
+ * s is NULL).  Valid until the next call on the handle. */
+const char *ij_last_error(const ij_sim *s);
+
+/* Bytes of ONE distribution buffer for the given parameters: 14 float
+ * planes of ny rows with a 64-float aligned row pitch (9 f, 5 g) and one
+ * 16-bit plane (low-order part of g_0). */
+ij_status ij_required_bytes(const ij_params *p, size_t *bytes);
+
+/* Use caller-owned device buffers (each >= ij_required_bytes, 256-byte
+ * aligned) instead of library allocations.  Ownership stays with the caller;
+ * they must outlive the handle.  Invalidates the current state (init again). */
+ij_status ij_attach_buffers(ij_sim *s, void *pdf_a, void *pdf_b, size_t bytes_each);
+
+/* Replace the wall mask: host array of ny*nx bytes, IJ_FLUID / IJ_WALL_INNER /
+ * IJ_WALL_OUTER.  With open rows, a fluid node of the bottom (top) row must
+ * have fluid directly above (below) it.  Invalidates the state. */
+ij_status ij_set_wall(ij_sim *s, const uint8_t *wall_host);
+
+/* Initial state from a signed distance d (device, [ny][nx], positive inside
+ * the ink): phi = phi* tanh(2 d / W), n = n0, u = 0, f = f_eq, g = g_eq
+ * (Eqs. 5-6, 9-10) with mu from this phi including the wetting ghosts.
+ * Sets t = 0 and clears the diagnostics. */
+ij_status ij_init_distance(ij_sim *s, const float *d_dev, void *stream);
+
+/* As ij_init_distance from phi itself (device, [ny][nx]) and an optional
+ * velocity (device arrays, NULL = 0). */
+ij_status ij_init_phi(ij_sim *s, const float *phi_dev, const float *ux_dev,
+                      const float *uy_dev, void *stream);
+
+/* Nozzle default: ink fills the rows y < nozzle_len (flat meniscus half a
+ * node above the last nozzle row). */
+ij_status ij_init_default(ij_sim *s, void *stream);
+
+/* Advance nsteps time steps (Eqs. 3-4 and 8 with the boundary rules), each a
+ * fused collide-stream launch; samples diagnostics every diag_every steps.
+ * Asynchronous.  Returns IJ_ERR_UNSTABLE without stepping once a checked
+ * sample has failed the guard (see ij_check). */
+ij_status ij_step(ij_sim *s, int64_t nsteps, void *stream);
+
+/* Same update as ij_step through the unfused reference kernels (phi and
+ * wetting ghosts written to a field, then one node per thread).  Slower;
+ * exists to cross-check the fused kernel. */
+ij_status ij_step_reference(ij_sim *s, int64_t nsteps, void *stream);
+
+/* Current time step. */
+int64_t ij_time(const ij_sim *s);
+
+/* Moments at the current step into caller device arrays [ny][nx] (NULL to
+ * skip): n, phi = sum g, and u = (sum c f + F/2)/n with the force of the
+ * current step.  Solid nodes receive 0. */
+ij_status ij_get_moments(ij_sim *s, float *n_dev, float *phi_dev, float *ux_dev,
+                         float *uy_dev, void *stream);
+
+/* Distributions of the current step into caller device arrays f [9][ny][nx]
+ * and g [5][ny][nx] (solid nodes hold unspecified values). */
+ij_status ij_get_state(ij_sim *s, float *f_dev, float *g_dev, void *stream);
+
+/* Overwrite the distributions (same layout) and the step counter. */
+ij_status ij_set_state(ij_sim *s, const float *f_dev, const float *g_dev, int64_t t,
+                       void *stream);
+
+/* Record one diagnostics sample at the current step (asynchronous): sums of
+ * n, phi and momentum, max |u|, non-finite count, and the per-row ink
+ * profile of rows >= diag_row0 split into segments. */
+ij_status ij_diag_sample(ij_sim *s, void *stream);
+
+/* Per-row ink count and summed u_y of the latest sample into host arrays of
+ * ny entries (rows below diag_row0 are 0).  Synchronises the stream. */
+ij_status ij_get_row_profile(ij_sim *s, int64_t *count_host, double *uy_host, void *stream);
+
+/* Copy up to cap recorded samples (oldest first) into host memory; *count
+ * receives the number recorded.  Synchronises the stream. */
+ij_status ij_get_samples(ij_sim *s, ij_sample *out_host, int64_t cap, int64_t *count,
+                         void *stream);
+
+/* Breakup step, drop velocity and volume, satellite flag and the latest
+ * sample.  Synchronises the stream. */
+ij_status ij_get_diagnostics(ij_sim *s, ij_diag *out, void *stream);
+
+/* Synchronise and check every sample recorded so far against the guard
+ * (non-finite values or max |u| > u_limit): IJ_OK or IJ_ERR_UNSTABLE. */
+ij_status ij_check(ij_sim *s, void *stream);
+
+/* Derived constants: out[0..7] = phi*, n0, beta, kappa, q, inner and outer
+ * wetting offsets 2 Omega phi_star / W, mobility Gamma q (q tau_phi - 1/2). */
+ij_status ij_derived(const ij_sim *s, double out[8]);
+
+/* Tile shape of the fused collide-stream kernel: waves across x per
+ * workgroup (1, 2 or 4) and rows per workgroup (>= 1).  0 keeps the
+ * current value. */
+ij_status ij_set_tiling(ij_sim *s, int32_t waves_x, int32_t rows_per_block);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* INKJET_LBM_H */

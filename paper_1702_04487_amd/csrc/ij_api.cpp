@@ -1,0 +1,623 @@
+// ij_api.cpp -- host side of the C ABI declared in include/inkjet_lbm.h:
+// parameter validation, derivation of the model constants (double precision,
+// rounded once to float), device memory, the step loop with the pulse
+// schedule, and the droplet-diagnostics summary.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "inkjet_lbm.h"
+#include "lbm_core.h"
+
+using ij::KParams;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr int kPitchAlign = 64;  // floats: 256-byte rows
+constexpr int64_t kSampleCap = 4096;
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+// one distribution buffer: 14 float planes and the 16-bit g_0 remainder plane
+size_t buffer_bytes(size_t plane) { return plane * (ij::kFloatPlanes * sizeof(float) + sizeof(uint16_t)); }
+
+}  // namespace
+
+struct ij_sim {
+    ij_params p{};
+    int nx = 0, ny = 0, pitch = 0;
+    size_t plane = 0;  // floats per plane
+    double phi_star = 0, n0 = 0, beta = 0, kappa = 0, q = 0, wet_in = 0, wet_out = 0;
+    KParams K{};
+    float* buf[2] = {nullptr, nullptr};
+    bool own[2] = {false, false};
+    int cur = 0;
+    uint8_t* wall = nullptr;   // device [ny][pitch]
+    std::vector<uint8_t> wall_host;  // [ny][nx]
+    double* phi = nullptr;     // device phi~ field [ny][pitch] (double)
+    int2* ghost = nullptr;     // solid nodes that touch fluid
+    int n_ghost = 0;
+    ij::DiagRow* rows = nullptr;
+    ij::SampleRec* samples = nullptr;  // device ring of kSampleCap
+    int64_t n_dev_samples = 0;         // recorded on the device, not yet drained
+    std::vector<ij_sample> host_samples;
+    int64_t t = 0;
+    bool initialised = false;
+    int64_t unstable_step = -1;
+    int waves_x = 4, rows_per_block = 64;
+    std::string err;
+};
+
+namespace {
+
+ij_status fail(ij_sim* s, ij_status st, const std::string& msg)
+{
+    if (s)
+        s->err = msg;
+    else
+        g_create_error = msg;
+    return st;
+}
+
+ij_status hip_fail(ij_sim* s, hipError_t e, const char* where)
+{
+    return fail(s, IJ_ERR_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define IJ_HIP(s, call)                                 \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) return hip_fail(s, e_, #call); \
+    } while (0)
+
+// Wetting parameter Omega from the contact angle (degrees, through the ink):
+// inverse of cos(theta) = [(1+Omega)^{3/2} - (1-Omega)^{3/2}]/2, the Cahn
+// wetting relation of the phi^4 free energy.  Closed form via the cubic in
+// cos(alpha/3) with alpha = arccos(sin^2 theta).
+double wetting_omega(double theta_deg)
+{
+    if (theta_deg == 90.0) return 0.0;
+    const double th = theta_deg * M_PI / 180.0;
+    const double s2 = std::sin(th) * std::sin(th);
+    const double c = std::cos(std::acos(std::min(1.0, s2)) / 3.0);
+    const double mag = 2.0 * std::sqrt(std::max(0.0, c * (1.0 - c)));
+    return theta_deg < 90.0 ? mag : -mag;
+}
+
+// Fig. 1 pulse: +f_pos on [0, t_pos), -f_neg on [t_pos, t_pos + t_neg), then
+// idle; periodic with period t_pos + t_neg + t_idle when requested.
+double pulse_value(const ij_params& p, int64_t t)
+{
+    const int64_t period = p.t_pos + p.t_neg + p.t_idle;
+    int64_t tt = t;
+    if (p.periodic_pulse && period > 0) tt = t % period;
+    if (tt < p.t_pos) return p.f_pos;
+    if (tt < p.t_pos + p.t_neg) return -p.f_neg;
+    return 0.0;
+}
+
+std::string validate(const ij_params& p)
+{
+    if (p.nx < 3 || p.ny < 3) return "nx and ny must be >= 3";
+    if (p.nx > (1 << 24) || p.ny > 65535) return "lattice dimension too large (ny <= 65535)";
+    if (p.bc_y != IJ_BC_PERIODIC && p.bc_y != IJ_BC_OPEN) return "bc_y must be IJ_BC_PERIODIC or IJ_BC_OPEN";
+    if (!(p.tau_ink > 0.5) || !(p.tau_amb > 0.5) || !(p.tau_phi > 0.5)) return "relaxation times must exceed 1/2";
+    if (!(p.rho_amb > 0.0) || !(p.rho_ink > p.rho_amb)) return "need rho_ink > rho_amb > 0";
+    if (!(p.width > 0.0)) return "interface width must be positive";
+    if (!(p.sigma >= 0.0)) return "surface tension must be >= 0";
+    if (!(p.gamma >= 0.0)) return "mobility Gamma must be >= 0";
+    if (!(p.theta_inner >= 0.0 && p.theta_inner <= 180.0) || !(p.theta_outer >= 0.0 && p.theta_outer <= 180.0))
+        return "contact angles must lie in [0, 180]";
+    if (p.t_pos < 0 || p.t_neg < 0 || p.t_idle < 0) return "pulse durations must be >= 0";
+    if (!std::isfinite(p.f_pos) || !std::isfinite(p.f_neg)) return "pulse amplitudes must be finite";
+    if (p.nozzle_w < 0 || (p.nozzle_w > 0 && (p.nozzle_x0 < 1 || p.nozzle_x0 + p.nozzle_w > p.nx - 1 ||
+                                               p.nozzle_len < 1 || p.nozzle_len > p.ny - 2)))
+        return "nozzle must lie inside the lattice with a wall column on each side";
+    if (p.diag_row0 < 0 || p.diag_row0 >= p.ny) return "diag_row0 outside the lattice";
+    if (p.diag_every < 0) return "diag_every must be >= 0";
+    const double planes = 15.0 * (double)p.ny * (double)round_up(p.nx, kPitchAlign);
+    if (planes >= 2147483647.0) return "lattice too large for 32-bit plane offsets";
+    return "";
+}
+
+std::string check_wall(const ij_params& p, const uint8_t* w)
+{
+    const int64_t nx = p.nx, ny = p.ny;
+    for (int64_t k = 0; k < nx * ny; ++k)
+        if (w[k] > 2) return "wall mask values must be 0, 1 or 2";
+    if (p.bc_y == IJ_BC_OPEN)
+        for (int64_t x = 0; x < nx; ++x) {
+            if (w[x] == 0 && w[nx + x] != 0) return "open bottom row: fluid node without fluid above";
+            if (w[(ny - 1) * nx + x] == 0 && w[(ny - 2) * nx + x] != 0)
+                return "open top row: fluid node without fluid below";
+        }
+    return "";
+}
+
+void build_nozzle(const ij_params& p, std::vector<uint8_t>& w)
+{
+    const int64_t nx = p.nx, ny = p.ny;
+    w.assign((size_t)(nx * ny), IJ_FLUID);
+    if (p.nozzle_w <= 0) return;
+    for (int64_t y = 0; y < p.nozzle_len; ++y)
+        for (int64_t x = 0; x < nx; ++x) {
+            uint8_t v = IJ_WALL_OUTER;
+            if (x >= p.nozzle_x0 && x < p.nozzle_x0 + p.nozzle_w) v = IJ_FLUID;
+            if (x == p.nozzle_x0 - 1 || x == p.nozzle_x0 + p.nozzle_w) v = IJ_WALL_INNER;
+            w[(size_t)(y * nx + x)] = v;
+        }
+}
+
+void fill_kparams(ij_sim* s)
+{
+    KParams& K = s->K;
+    const ij_params& p = s->p;
+    K.nx = s->nx;
+    K.ny = s->ny;
+    K.pitch = s->pitch;
+    K.bc_open = p.bc_y == IJ_BC_OPEN;
+    K.force_rows = (int)std::min<int64_t>(p.force_rows, s->ny);
+    K.plane = (unsigned)s->plane;
+    K.phi_star = s->phi_star;
+    K.beta4 = 4.0 * s->beta;
+    K.kappa = s->kappa;
+    K.gamma = p.gamma;
+    K.omega_phi = 1.0 / p.tau_phi;
+    K.inv_width = 1.0 / p.width;
+    K.wet[0] = 0.0;
+    K.wet[1] = s->wet_in;
+    K.wet[2] = s->wet_out;
+    K.wet[3] = 0.0;
+    K.n0 = (float)s->n0;
+    K.inv_phi_star = (float)(1.0 / s->phi_star);
+    K.tau_amb = (float)p.tau_amb;
+    K.dtau = (float)(p.tau_ink - p.tau_amb);
+    K.omq = (float)(1.0 - s->q);
+    K.c_half_q = (float)(1.0 / (2.0 * s->q));
+    K.omega_phi_f = (float)(1.0 / p.tau_phi);
+    K.gamma_f = (float)p.gamma;
+    K.fb = 0.f;
+}
+
+ij_status upload_wall(ij_sim* s)
+{
+    // padded device copy and the list of solid nodes with a fluid neighbour
+    std::vector<uint8_t> padded((size_t)s->ny * s->pitch, IJ_WALL_OUTER);
+    for (int y = 0; y < s->ny; ++y)
+        std::memcpy(&padded[(size_t)y * s->pitch], &s->wall_host[(size_t)y * s->nx], (size_t)s->nx);
+    IJ_HIP(s, hipMemcpy(s->wall, padded.data(), padded.size(), hipMemcpyHostToDevice));
+    std::vector<int2> list;
+    const bool open = s->p.bc_y == IJ_BC_OPEN;
+    for (int y = 0; y < s->ny; ++y)
+        for (int x = 0; x < s->nx; ++x) {
+            if (s->wall_host[(size_t)y * s->nx + x] == 0) continue;
+            bool touches = false;
+            for (int dy = -1; dy <= 1 && !touches; ++dy)
+                for (int dx = -1; dx <= 1 && !touches; ++dx) {
+                    int yy = y + dy;
+                    if (yy < 0 || yy >= s->ny) {
+                        if (open) continue;
+                        yy = (yy + s->ny) % s->ny;
+                    }
+                    const int xx = (x + dx + s->nx) % s->nx;
+                    if (s->wall_host[(size_t)yy * s->nx + xx] == 0) touches = true;
+                }
+            if (touches) list.push_back(make_int2(x, y));
+        }
+    if (s->ghost) {
+        (void)hipFree(s->ghost);
+        s->ghost = nullptr;
+    }
+    s->n_ghost = (int)list.size();
+    if (s->n_ghost) {
+        if (hipMalloc(&s->ghost, list.size() * sizeof(int2)) != hipSuccess)
+            return fail(s, IJ_ERR_OOM, "ghost list allocation failed");
+        IJ_HIP(s, hipMemcpy(s->ghost, list.data(), list.size() * sizeof(int2), hipMemcpyHostToDevice));
+    }
+    s->initialised = false;
+    return IJ_OK;
+}
+
+ij_status drain_samples(ij_sim* s, hipStream_t st)
+{
+    if (s->n_dev_samples == 0) return IJ_OK;
+    std::vector<ij::SampleRec> tmp((size_t)s->n_dev_samples);
+    IJ_HIP(s, hipMemcpyAsync(tmp.data(), s->samples, tmp.size() * sizeof(ij::SampleRec), hipMemcpyDeviceToHost, st));
+    IJ_HIP(s, hipStreamSynchronize(st));
+    static_assert(sizeof(ij::SampleRec) == sizeof(ij_sample), "sample layouts differ");
+    for (const auto& r : tmp) {
+        ij_sample o;
+        std::memcpy(&o, &r, sizeof o);
+        s->host_samples.push_back(o);
+        const double lim = s->p.u_limit > 0 ? s->p.u_limit : 0.3;
+        if (s->unstable_step < 0 && (o.nan_count > 0 || !(o.max_u <= lim))) s->unstable_step = o.step;
+    }
+    s->n_dev_samples = 0;
+    return IJ_OK;
+}
+
+ij_status record_sample(ij_sim* s, hipStream_t st)
+{
+    if (s->n_dev_samples >= kSampleCap) {
+        ij_status r = drain_samples(s, st);
+        if (r != IJ_OK) return r;
+    }
+    s->K.fb = (float)pulse_value(s->p, s->t);
+    hipError_t e = ij::launch_phi_ghost(s->K, s->buf[s->cur], s->wall, s->phi, s->ghost, s->n_ghost, st);
+    if (e != hipSuccess) return hip_fail(s, e, "phi/ghost kernels");
+    const int a_min = (int)std::ceil(4.0 * s->p.width * s->p.width);
+    e = ij::launch_diag(s->K, s->buf[s->cur], s->wall, s->phi, (int)s->p.diag_row0, a_min, s->t, s->rows,
+                        s->samples + s->n_dev_samples, st);
+    if (e != hipSuccess) return hip_fail(s, e, "diagnostics kernels");
+    s->n_dev_samples += 1;
+    return IJ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ij_status ij_params_default(ij_params* p)
+{
+    if (!p) return IJ_ERR_INVALID_ARG;
+    std::memset(p, 0, sizeof *p);
+    p->nx = 64;
+    p->ny = 256;
+    p->bc_y = IJ_BC_OPEN;
+    p->nozzle_x0 = 24;
+    p->nozzle_w = 16;
+    p->nozzle_len = 64;
+    p->force_rows = 64;
+    p->diag_row0 = 64;
+    p->rho_ink = 1.0;
+    p->rho_amb = 0.1;
+    p->sigma = 0.01;
+    p->width = 4.0;
+    p->gamma = 1.0;
+    p->tau_ink = p->tau_amb = p->tau_phi = 1.0;
+    p->theta_inner = p->theta_outer = 90.0;
+    p->u_limit = 0.3;
+    return IJ_OK;
+}
+
+ij_status ij_required_bytes(const ij_params* p, size_t* bytes)
+{
+    if (!p || !bytes) return IJ_ERR_INVALID_ARG;
+    const std::string v = validate(*p);
+    if (!v.empty()) return fail(nullptr, IJ_ERR_INVALID_ARG, v);
+    *bytes = buffer_bytes((size_t)p->ny * (size_t)round_up(p->nx, kPitchAlign));
+    return IJ_OK;
+}
+
+ij_status ij_create(const ij_params* p, ij_sim** out)
+{
+    if (!out) return fail(nullptr, IJ_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!p) return fail(nullptr, IJ_ERR_INVALID_ARG, "params is NULL");
+    const std::string v = validate(*p);
+    if (!v.empty()) return fail(nullptr, IJ_ERR_INVALID_ARG, v);
+
+    ij_sim* s = new ij_sim();
+    s->p = *p;
+    s->nx = (int)p->nx;
+    s->ny = (int)p->ny;
+    s->pitch = (int)round_up(p->nx, kPitchAlign);
+    s->plane = (size_t)s->ny * s->pitch;
+    // composition variables (Eqs. 1, 7): n = (rho_A + rho_B)/2, phi = (rho_A - rho_B)/2
+    s->phi_star = 0.5 * (p->rho_ink - p->rho_amb);
+    s->n0 = 0.5 * (p->rho_ink + p->rho_amb);
+    // phi^4 closure: profile phi* tanh(2z/W) with tension sigma
+    const double ps2 = s->phi_star * s->phi_star;
+    s->beta = 3.0 * p->sigma / (4.0 * p->width * ps2 * ps2);
+    s->kappa = 3.0 * p->sigma * p->width / (8.0 * ps2);
+    s->q = 1.0 / (p->tau_phi + 0.5);
+    s->wet_in = 2.0 * wetting_omega(p->theta_inner) * s->phi_star / p->width;
+    s->wet_out = 2.0 * wetting_omega(p->theta_outer) * s->phi_star / p->width;
+    if (s->p.force_rows == 0 && p->nozzle_w > 0) s->p.force_rows = p->nozzle_len;
+    s->waves_x = 1;
+    fill_kparams(s);
+
+    const size_t bytes = buffer_bytes(s->plane);
+    auto cleanup = [&](ij_status st, const std::string& m) {
+        const std::string msg = m;
+        ij_destroy(s);
+        return fail(nullptr, st, msg);
+    };
+    for (int b = 0; b < 2; ++b) {
+        if (hipMalloc(&s->buf[b], bytes) != hipSuccess) return cleanup(IJ_ERR_OOM, "distribution buffer allocation failed");
+        s->own[b] = true;
+    }
+    if (hipMalloc(&s->wall, s->plane) != hipSuccess || hipMalloc(&s->phi, s->plane * sizeof(double)) != hipSuccess ||
+        hipMalloc(&s->rows, (size_t)s->ny * sizeof(ij::DiagRow)) != hipSuccess ||
+        hipMalloc(&s->samples, (size_t)kSampleCap * sizeof(ij::SampleRec)) != hipSuccess)
+        return cleanup(IJ_ERR_OOM, "scratch allocation failed");
+    if (hipMemset(s->phi, 0, s->plane * sizeof(double)) != hipSuccess)
+        return cleanup(IJ_ERR_DEVICE, "hipMemset failed");
+    build_nozzle(s->p, s->wall_host);
+    const std::string wv = check_wall(s->p, s->wall_host.data());
+    if (!wv.empty()) return cleanup(IJ_ERR_INVALID_ARG, wv);
+    if (upload_wall(s) != IJ_OK) return cleanup(IJ_ERR_DEVICE, s->err);
+    *out = s;
+    return IJ_OK;
+}
+
+void ij_destroy(ij_sim* s)
+{
+    if (!s) return;
+    for (int b = 0; b < 2; ++b)
+        if (s->own[b] && s->buf[b]) (void)hipFree(s->buf[b]);
+    if (s->wall) (void)hipFree(s->wall);
+    if (s->phi) (void)hipFree(s->phi);
+    if (s->ghost) (void)hipFree(s->ghost);
+    if (s->rows) (void)hipFree(s->rows);
+    if (s->samples) (void)hipFree(s->samples);
+    delete s;
+}
+
+const char* ij_last_error(const ij_sim* s) { return s ? s->err.c_str() : g_create_error.c_str(); }
+
+ij_status ij_attach_buffers(ij_sim* s, void* a, void* b, size_t bytes_each)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (!a || !b || a == b) return fail(s, IJ_ERR_INVALID_ARG, "need two distinct device buffers");
+    const size_t need = buffer_bytes(s->plane);
+    if (bytes_each < need) return fail(s, IJ_ERR_INVALID_ARG, "buffers smaller than ij_required_bytes");
+    if (((uintptr_t)a & 255) || ((uintptr_t)b & 255)) return fail(s, IJ_ERR_INVALID_ARG, "buffers must be 256-byte aligned");
+    for (int k = 0; k < 2; ++k)
+        if (s->own[k] && s->buf[k]) {
+            (void)hipFree(s->buf[k]);
+            s->own[k] = false;
+        }
+    s->buf[0] = (float*)a;
+    s->buf[1] = (float*)b;
+    s->cur = 0;
+    s->initialised = false;
+    return IJ_OK;
+}
+
+ij_status ij_set_wall(ij_sim* s, const uint8_t* w)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (!w) return fail(s, IJ_ERR_INVALID_ARG, "wall is NULL");
+    const std::string v = check_wall(s->p, w);
+    if (!v.empty()) return fail(s, IJ_ERR_INVALID_ARG, v);
+    s->wall_host.assign(w, w + (size_t)s->nx * s->ny);
+    return upload_wall(s);
+}
+
+static ij_status do_init(ij_sim* s, const float* src, int from_distance, const float* ux, const float* uy,
+                         void* stream)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (!src) return fail(s, IJ_ERR_INVALID_ARG, "initial field is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    s->cur = 0;
+    s->t = 0;
+    s->K.fb = 0.f;
+    hipError_t e = ij::launch_init(s->K, s->buf[0], s->wall, s->phi, src, from_distance, ux, uy, s->ghost,
+                                   s->n_ghost, st);
+    if (e != hipSuccess) return hip_fail(s, e, "init kernels");
+    s->host_samples.clear();
+    s->n_dev_samples = 0;
+    s->unstable_step = -1;
+    s->initialised = true;
+    return IJ_OK;
+}
+
+ij_status ij_init_distance(ij_sim* s, const float* d, void* stream) { return do_init(s, d, 1, nullptr, nullptr, stream); }
+
+ij_status ij_init_phi(ij_sim* s, const float* phi, const float* ux, const float* uy, void* stream)
+{
+    return do_init(s, phi, 0, ux, uy, stream);
+}
+
+ij_status ij_init_default(ij_sim* s, void* stream)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    const int64_t L = s->p.nozzle_w > 0 ? s->p.nozzle_len : s->ny / 4;
+    std::vector<float> d((size_t)s->nx * s->ny);
+    for (int y = 0; y < s->ny; ++y)
+        for (int x = 0; x < s->nx; ++x) d[(size_t)y * s->nx + x] = (float)((double)L - 0.5 - y);
+    float* dd = nullptr;
+    IJ_HIP(s, hipMalloc(&dd, d.size() * sizeof(float)));
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(dd, d.data(), d.size() * sizeof(float), hipMemcpyHostToDevice, st);
+    ij_status r = e == hipSuccess ? do_init(s, dd, 1, nullptr, nullptr, stream) : hip_fail(s, e, "hipMemcpyAsync");
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(dd);
+    return r;
+}
+
+ij_status ij_step(ij_sim* s, int64_t nsteps, void* stream)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (!s->initialised) return fail(s, IJ_ERR_STATE, "step before init");
+    if (nsteps < 0) return fail(s, IJ_ERR_INVALID_ARG, "nsteps < 0");
+    if (s->unstable_step >= 0) return fail(s, IJ_ERR_UNSTABLE, "a diagnostics sample failed the stability guard");
+    hipStream_t st = (hipStream_t)stream;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        if (s->p.diag_every > 0 && s->t % s->p.diag_every == 0) {
+            ij_status r = record_sample(s, st);
+            if (r != IJ_OK) return r;
+        }
+        s->K.fb = (float)pulse_value(s->p, s->t);
+        hipError_t e = ij::launch_collide_fused(s->K, s->buf[s->cur], s->buf[1 - s->cur], s->wall, s->waves_x,
+                                                s->rows_per_block, st);
+        if (e != hipSuccess) return hip_fail(s, e, "collide-stream kernel");
+        s->cur = 1 - s->cur;
+        s->t += 1;
+    }
+    return IJ_OK;
+}
+
+// Reference path (one node per thread, phi round trip through memory); kept
+// for cross-checking the fused kernel.
+ij_status ij_step_reference(ij_sim* s, int64_t nsteps, void* stream)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (!s->initialised) return fail(s, IJ_ERR_STATE, "step before init");
+    hipStream_t st = (hipStream_t)stream;
+    for (int64_t k = 0; k < nsteps; ++k) {
+        s->K.fb = (float)pulse_value(s->p, s->t);
+        hipError_t e = ij::launch_phi_ghost(s->K, s->buf[s->cur], s->wall, s->phi, s->ghost, s->n_ghost, st);
+        if (e == hipSuccess)
+            e = ij::launch_collide_ref(s->K, s->buf[s->cur], s->buf[1 - s->cur], s->wall, s->phi, st);
+        if (e != hipSuccess) return hip_fail(s, e, "reference kernels");
+        s->cur = 1 - s->cur;
+        s->t += 1;
+    }
+    return IJ_OK;
+}
+
+int64_t ij_time(const ij_sim* s) { return s ? s->t : -1; }
+
+ij_status ij_get_moments(ij_sim* s, float* n, float* ph, float* ux, float* uy, void* stream)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (!s->initialised) return fail(s, IJ_ERR_STATE, "moments before init");
+    hipStream_t st = (hipStream_t)stream;
+    s->K.fb = (float)pulse_value(s->p, s->t);
+    hipError_t e = ij::launch_phi_ghost(s->K, s->buf[s->cur], s->wall, s->phi, s->ghost, s->n_ghost, st);
+    if (e == hipSuccess) e = ij::launch_moments(s->K, s->buf[s->cur], s->wall, s->phi, n, ph, ux, uy, st);
+    if (e != hipSuccess) return hip_fail(s, e, "moment kernels");
+    return IJ_OK;
+}
+
+ij_status ij_get_state(ij_sim* s, float* f, float* g, void* stream)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (!s->initialised) return fail(s, IJ_ERR_STATE, "state before init");
+    hipError_t e = ij::launch_state_io(s->K, s->buf[s->cur], f, g, 1, (hipStream_t)stream);
+    return e == hipSuccess ? IJ_OK : hip_fail(s, e, "state readback kernel");
+}
+
+ij_status ij_set_state(ij_sim* s, const float* f, const float* g, int64_t t, void* stream)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (!f || !g) return fail(s, IJ_ERR_INVALID_ARG, "f and g are required");
+    if (t < 0) return fail(s, IJ_ERR_INVALID_ARG, "t < 0");
+    hipError_t e = ij::launch_state_io(s->K, s->buf[s->cur], (float*)f, (float*)g, 0, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(s, e, "state write kernel");
+    s->t = t;
+    s->initialised = true;
+    return IJ_OK;
+}
+
+ij_status ij_diag_sample(ij_sim* s, void* stream)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (!s->initialised) return fail(s, IJ_ERR_STATE, "diagnostics before init");
+    return record_sample(s, (hipStream_t)stream);
+}
+
+ij_status ij_get_row_profile(ij_sim* s, int64_t* count, double* uy, void* stream)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (s->n_dev_samples == 0 && s->host_samples.empty()) return fail(s, IJ_ERR_STATE, "no diagnostics sample yet");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<ij::DiagRow> rows((size_t)s->ny);
+    IJ_HIP(s, hipMemcpyAsync(rows.data(), s->rows, rows.size() * sizeof(ij::DiagRow), hipMemcpyDeviceToHost, st));
+    IJ_HIP(s, hipStreamSynchronize(st));
+    for (int y = 0; y < s->ny; ++y) {
+        if (count) count[y] = rows[(size_t)y].count;
+        if (uy) uy[y] = rows[(size_t)y].uy;
+    }
+    return IJ_OK;
+}
+
+ij_status ij_get_samples(ij_sim* s, ij_sample* out, int64_t cap, int64_t* count, void* stream)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    ij_status r = drain_samples(s, (hipStream_t)stream);
+    if (r != IJ_OK) return r;
+    const int64_t n = (int64_t)s->host_samples.size();
+    if (count) *count = n;
+    if (out)
+        for (int64_t k = 0; k < std::min(n, cap); ++k) out[k] = s->host_samples[(size_t)k];
+    return IJ_OK;
+}
+
+ij_status ij_check(ij_sim* s, void* stream)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    ij_status r = drain_samples(s, (hipStream_t)stream);
+    if (r != IJ_OK) return r;
+    return s->unstable_step >= 0 ? fail(s, IJ_ERR_UNSTABLE, "a diagnostics sample failed the stability guard") : IJ_OK;
+}
+
+ij_status ij_get_diagnostics(ij_sim* s, ij_diag* out, void* stream)
+{
+    if (!s || !out) return IJ_ERR_INVALID_ARG;
+    ij_status r = drain_samples(s, (hipStream_t)stream);
+    if (r != IJ_OK) return r;
+    std::memset(out, 0, sizeof *out);
+    out->step = s->t;
+    out->n_samples = (int64_t)s->host_samples.size();
+    out->unstable_step = s->unstable_step;
+    out->breakup_step = -1;
+    out->v_drop = NAN;
+    out->last.largest_top = -1;
+    if (s->host_samples.empty()) return IJ_OK;
+    out->last = s->host_samples.back();
+    // breakup: first sample with a detached drop
+    int64_t tb = -1;
+    for (const auto& x : s->host_samples)
+        if (x.n_detached > 0) {
+            tb = x.step;
+            break;
+        }
+    out->breakup_step = tb;
+    if (tb < 0) return IJ_OK;
+    // drop velocity: mean of the largest drop's mean u_y over [tb+1000, tb+3000],
+    // stopping once its top comes within 2W of the last row
+    double acc = 0.0;
+    int64_t nv = 0;
+    for (const auto& x : s->host_samples) {
+        if (x.step < tb + 1000 || x.step > tb + 3000 || x.largest_count <= 0) continue;
+        if ((double)x.largest_top >= (double)(s->ny - 1) - 2.0 * s->p.width) break;
+        acc += x.largest_uy / (double)x.largest_count;
+        ++nv;
+    }
+    if (nv) out->v_drop = acc / (double)nv;
+    for (const auto& x : s->host_samples)
+        if (x.step >= tb + 2000) {
+            out->vol_drop = x.largest_count;
+            out->satellite = x.n_detached >= 2;
+            break;
+        }
+    return IJ_OK;
+}
+
+ij_status ij_derived(const ij_sim* s, double out[8])
+{
+    if (!s || !out) return IJ_ERR_INVALID_ARG;
+    out[0] = s->phi_star;
+    out[1] = s->n0;
+    out[2] = s->beta;
+    out[3] = s->kappa;
+    out[4] = s->q;
+    out[5] = s->wet_in;
+    out[6] = s->wet_out;
+    out[7] = s->p.gamma * s->q * (s->q * s->p.tau_phi - 0.5);
+    return IJ_OK;
+}
+
+ij_status ij_set_tiling(ij_sim* s, int32_t waves_x, int32_t rows_per_block)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (waves_x != 0 && waves_x != 1 && waves_x != 2 && waves_x != 4)
+        return fail(s, IJ_ERR_INVALID_ARG, "waves_x must be 1, 2 or 4");
+    if (rows_per_block < 0) return fail(s, IJ_ERR_INVALID_ARG, "rows_per_block must be >= 0");
+    if (waves_x) s->waves_x = waves_x;
+    if (rows_per_block) s->rows_per_block = rows_per_block;
+    return IJ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,282 @@
+"""Python binding of the C ABI in ``include/inkjet_lbm.h`` (ctypes).
+
+Argument marshalling only: every step of the update runs in the HIP library
+``libinkjet_lbm.so``.  PyTorch provides device memory and streams; tensors
+are passed to the library as raw device pointers on torch's current stream.
+The module raises when the library is missing - there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libinkjet_lbm.so")
+
+IJ_OK, IJ_ERR_INVALID_ARG, IJ_ERR_OOM, IJ_ERR_DEVICE, IJ_ERR_UNSTABLE, IJ_ERR_STATE = 0, -1, -2, -3, -4, -5
+BC_PERIODIC, BC_OPEN = 0, 1
+
+_INT_FIELDS = ["nx", "ny", "bc_y", "force_rows", "t_pos", "t_neg", "t_idle", "periodic_pulse",
+               "nozzle_x0", "nozzle_w", "nozzle_len", "diag_row0", "diag_every"]
+_DBL_FIELDS = ["rho_ink", "rho_amb", "sigma", "width", "gamma", "tau_ink", "tau_amb", "tau_phi",
+               "theta_inner", "theta_outer", "f_pos", "f_neg", "u_limit"]
+
+
+class IJParams(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in _INT_FIELDS] + [(k, ctypes.c_double) for k in _DBL_FIELDS]
+
+
+class IJSample(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("mass_n", ctypes.c_double), ("mass_phi", ctypes.c_double),
+                ("mom_x", ctypes.c_double), ("mom_y", ctypes.c_double), ("max_u", ctypes.c_double),
+                ("nan_count", ctypes.c_int64), ("n_detached", ctypes.c_int64),
+                ("largest_count", ctypes.c_int64), ("largest_uy", ctypes.c_double),
+                ("largest_top", ctypes.c_int64)]
+
+
+class IJDiag(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("n_samples", ctypes.c_int64), ("breakup_step", ctypes.c_int64),
+                ("v_drop", ctypes.c_double), ("vol_drop", ctypes.c_int64), ("satellite", ctypes.c_int64),
+                ("unstable_step", ctypes.c_int64), ("last", IJSample)]
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"inkjet_lbm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+# every symbol the header declares (checked by the CPU test-suite)
+EXPORTS = ["ij_params_default", "ij_create", "ij_destroy", "ij_last_error", "ij_required_bytes",
+           "ij_attach_buffers", "ij_set_wall", "ij_init_distance", "ij_init_phi", "ij_init_default",
+           "ij_step", "ij_step_reference", "ij_time", "ij_get_moments", "ij_get_state", "ij_set_state",
+           "ij_diag_sample", "ij_get_row_profile", "ij_get_samples", "ij_get_diagnostics", "ij_check",
+           "ij_derived", "ij_set_tiling"]
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FileNotFoundError(f"{path} is missing: build it with `python -m paper_1702_04487_amd.build`")
+    L = ctypes.CDLL(path)
+    vp, i64, i32, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+    sig = {
+        "ij_params_default": (st, [ctypes.POINTER(IJParams)]),
+        "ij_create": (st, [ctypes.POINTER(IJParams), ctypes.POINTER(vp)]),
+        "ij_destroy": (None, [vp]),
+        "ij_last_error": (ctypes.c_char_p, [vp]),
+        "ij_required_bytes": (st, [ctypes.POINTER(IJParams), ctypes.POINTER(ctypes.c_size_t)]),
+        "ij_attach_buffers": (st, [vp, vp, vp, ctypes.c_size_t]),
+        "ij_set_wall": (st, [vp, vp]),
+        "ij_init_distance": (st, [vp, vp, vp]),
+        "ij_init_phi": (st, [vp, vp, vp, vp, vp]),
+        "ij_init_default": (st, [vp, vp]),
+        "ij_step": (st, [vp, i64, vp]),
+        "ij_step_reference": (st, [vp, i64, vp]),
+        "ij_time": (i64, [vp]),
+        "ij_get_moments": (st, [vp, vp, vp, vp, vp, vp]),
+        "ij_get_state": (st, [vp, vp, vp, vp]),
+        "ij_set_state": (st, [vp, vp, vp, i64, vp]),
+        "ij_diag_sample": (st, [vp, vp]),
+        "ij_get_row_profile": (st, [vp, vp, vp, vp]),
+        "ij_get_samples": (st, [vp, ctypes.POINTER(IJSample), i64, ctypes.POINTER(i64), vp]),
+        "ij_get_diagnostics": (st, [vp, ctypes.POINTER(IJDiag), vp]),
+        "ij_check": (st, [vp, vp]),
+        "ij_derived": (st, [vp, ctypes.POINTER(ctypes.c_double)]),
+        "ij_set_tiling": (st, [vp, i32, i32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def to_params(d: dict) -> IJParams:
+    p = IJParams()
+    load().ij_params_default(ctypes.byref(p))
+    # a dict without nozzle fields describes an all-fluid lattice (walls come from set_wall)
+    p.nozzle_w = 0
+    p.nozzle_x0 = 0
+    p.nozzle_len = 0
+    p.diag_row0 = 0
+    for k in _INT_FIELDS + _DBL_FIELDS:
+        if k in d:
+            setattr(p, k, d[k])
+    return p
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t) -> Optional[ctypes.c_void_p]:
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous() and t.dtype.is_floating_point
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Sim:
+    """One lattice on the GPU, owned by the library (or by caller tensors
+    passed to :meth:`attach`)."""
+
+    def __init__(self, params: dict, wall: Optional[np.ndarray] = None):
+        import torch
+        self.L = load()
+        self.params = dict(params)
+        self.nx, self.ny = int(params["nx"]), int(params["ny"])
+        self._p = to_params(params)
+        h = ctypes.c_void_p()
+        r = self.L.ij_create(ctypes.byref(self._p), ctypes.byref(h))
+        if r != IJ_OK:
+            raise LBMError(r, self.L.ij_last_error(None).decode())
+        self.h = h
+        self._keep = []
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        if wall is not None:
+            self.set_wall(wall)
+
+    def _check(self, r: int):
+        if r != IJ_OK:
+            raise LBMError(r, self.L.ij_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ij_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ set-up
+    def set_wall(self, wall: np.ndarray):
+        w = np.ascontiguousarray(wall, dtype=np.uint8)
+        assert w.shape == (self.ny, self.nx)
+        self._check(self.L.ij_set_wall(self.h, w.ctypes.data_as(ctypes.c_void_p)))
+
+    def set_tiling(self, waves_x: int = 0, rows_per_block: int = 0):
+        self._check(self.L.ij_set_tiling(self.h, int(waves_x), int(rows_per_block)))
+
+    def attach(self, a, b):
+        """Use two caller tensors (torch, uint8/float, contiguous, on the
+        device) as the distribution buffers."""
+        need = self.required_bytes()
+        for t in (a, b):
+            assert t.is_cuda and t.is_contiguous() and t.numel() * t.element_size() >= need
+        self._keep = [a, b]
+        self._check(self.L.ij_attach_buffers(self.h, ctypes.c_void_p(a.data_ptr()),
+                                             ctypes.c_void_p(b.data_ptr()), need))
+
+    def required_bytes(self) -> int:
+        n = ctypes.c_size_t(0)
+        r = self.L.ij_required_bytes(ctypes.byref(self._p), ctypes.byref(n))
+        if r != IJ_OK:
+            raise LBMError(r, self.L.ij_last_error(None).decode())
+        return int(n.value)
+
+    def derived(self) -> dict:
+        out = (ctypes.c_double * 8)()
+        self._check(self.L.ij_derived(self.h, out))
+        keys = ["phi_star", "n0", "beta", "kappa", "q", "wet_inner", "wet_outer", "mobility"]
+        return dict(zip(keys, list(out)))
+
+    def _dev(self, a, shape=None):
+        """float32 contiguous device copy, checked against the shape the
+        kernels will index ([ny][nx] unless given)."""
+        import torch
+        if isinstance(a, torch.Tensor):
+            t = a.to(device=self.device, dtype=torch.float32).contiguous()
+        else:
+            t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=self.device)
+        want = tuple(shape) if shape is not None else (self.ny, self.nx)
+        if tuple(t.shape) != want:
+            raise ValueError(f"array of shape {tuple(t.shape)} where {want} is required")
+        return t
+
+    def init_distance(self, d, stream=None):
+        dd = self._dev(d)
+        self._check(self.L.ij_init_distance(self.h, _dptr(dd), _stream_ptr(stream)))
+        self._keep_init = dd
+
+    def init_phi(self, phi, ux=None, uy=None, stream=None):
+        p, x, y = self._dev(phi), None if ux is None else self._dev(ux), None if uy is None else self._dev(uy)
+        self._check(self.L.ij_init_phi(self.h, _dptr(p), _dptr(x), _dptr(y), _stream_ptr(stream)))
+        self._keep_init = (p, x, y)
+
+    def init_default(self, stream=None):
+        self._check(self.L.ij_init_default(self.h, _stream_ptr(stream)))
+
+    # ------------------------------------------------------------ stepping
+    def step(self, n: int = 1, stream=None):
+        self._check(self.L.ij_step(self.h, int(n), _stream_ptr(stream)))
+
+    def step_reference(self, n: int = 1, stream=None):
+        self._check(self.L.ij_step_reference(self.h, int(n), _stream_ptr(stream)))
+
+    @property
+    def t(self) -> int:
+        return int(self.L.ij_time(self.h))
+
+    # ------------------------------------------------------------ readback
+    def moments(self, stream=None) -> dict:
+        import torch
+        out = {k: torch.empty((self.ny, self.nx), device=self.device, dtype=torch.float32)
+               for k in ("n", "phi", "ux", "uy")}
+        self._check(self.L.ij_get_moments(self.h, _dptr(out["n"]), _dptr(out["phi"]), _dptr(out["ux"]),
+                                          _dptr(out["uy"]), _stream_ptr(stream)))
+        return out
+
+    def state(self, stream=None):
+        import torch
+        f = torch.empty((9, self.ny, self.nx), device=self.device, dtype=torch.float32)
+        g = torch.empty((5, self.ny, self.nx), device=self.device, dtype=torch.float32)
+        self._check(self.L.ij_get_state(self.h, _dptr(f), _dptr(g), _stream_ptr(stream)))
+        return f, g
+
+    def set_state(self, f, g, t: int = 0, stream=None):
+        ff, gg = self._dev(f, (9, self.ny, self.nx)), self._dev(g, (5, self.ny, self.nx))
+        self._check(self.L.ij_set_state(self.h, _dptr(ff), _dptr(gg), int(t), _stream_ptr(stream)))
+        self._keep_state = (ff, gg)
+
+    def diag_sample(self, stream=None):
+        self._check(self.L.ij_diag_sample(self.h, _stream_ptr(stream)))
+
+    def row_profile(self, stream=None):
+        cnt = np.zeros(self.ny, dtype=np.int64)
+        uy = np.zeros(self.ny, dtype=np.float64)
+        self._check(self.L.ij_get_row_profile(self.h, cnt.ctypes.data_as(ctypes.c_void_p),
+                                              uy.ctypes.data_as(ctypes.c_void_p), _stream_ptr(stream)))
+        return cnt, uy
+
+    def samples(self, stream=None) -> list:
+        n = ctypes.c_int64(0)
+        self._check(self.L.ij_get_samples(self.h, None, 0, ctypes.byref(n), _stream_ptr(stream)))
+        arr = (IJSample * max(1, n.value))()
+        self._check(self.L.ij_get_samples(self.h, arr, n.value, ctypes.byref(n), _stream_ptr(stream)))
+        return [{k: getattr(arr[i], k) for k, _ in IJSample._fields_} for i in range(n.value)]
+
+    def diagnostics(self, stream=None) -> dict:
+        d = IJDiag()
+        self._check(self.L.ij_get_diagnostics(self.h, ctypes.byref(d), _stream_ptr(stream)))
+        out = {k: getattr(d, k) for k, _ in IJDiag._fields_ if k != "last"}
+        out["last"] = {k: getattr(d.last, k) for k, _ in IJSample._fields_}
+        return out
+
+    def check(self, stream=None) -> int:
+        return int(self.L.ij_check(self.h, _stream_ptr(stream)))

@@ -183,15 +183,16 @@ def config_nozzle_single() -> dict:
 def config_droplet_field(nx: int = 2048, ny: int = 16384, seed: int = 0,
                          with_distance: bool = True) -> dict:
     """Roofline stress: seeded disc field (radii 8-64, ink area >= 25 %),
-    periodic in x and y, one solid row y = 0 as a flat wetting wall at 120
-    deg, no driving force, tau 0.8 ink / 1.0 ambient, 5000 steps."""
+    periodic in x and y, a flat wetting wall at 120 deg in rows y = 0, 1 (two
+    rows, so that each face of the wall sees only its own side), no driving
+    force, tau 0.8 ink / 1.0 ambient, 5000 steps."""
     p = base_params(nx, ny, bc_y=BC_PERIODIC, force_rows=ny, tau_ink=0.8,
                     theta_inner=120.0, theta_outer=120.0)
-    cfg = dict(name=f"droplets_{nx}x{ny}", params=p, wall=flat_wall(nx, ny, (0,)), row0=1,
+    cfg = dict(name=f"droplets_{nx}x{ny}", params=p, wall=flat_wall(nx, ny, (0, 1)), row0=2,
                steps=5000, nozzle=None)
     if with_distance:
         discs = sample_discs(nx, ny, seed=seed, rmin=8.0, rmax=min(64.0, ny / 8, nx / 8),
-                             gap=p["width"], area_frac=0.25, y_lo=1.0)
+                             gap=p["width"], area_frac=0.25, y_lo=2.0)
         cfg["discs"] = discs
         cfg["distance"] = discs_distance(nx, ny, discs, periodic=True)
     return cfg
