@@ -63,6 +63,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-steps", type=int, default=500,
                     help="launches timed back-to-back for the fused kernel's mean duration")
+    ap.add_argument("--tiling", default="",
+                    help="waves_x,rows_per_block of the fused kernel (default: the library's choice)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -78,6 +80,9 @@ def main() -> int:
     nx, ny = p["nx"], p["ny"]
     fluid_nodes = int((cfg["wall"] == 0).sum())
     sim = lbm.Sim(p, cfg["wall"])
+    if args.tiling:
+        wx, rows = (int(v) for v in args.tiling.split(","))
+        sim.set_tiling(wx, rows)
     sim.init_distance(cfg["distance"])
     stream = torch.cuda.current_stream()
 
@@ -134,7 +139,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"droplet field {nx}x{ny} (seeded discs r 8-64, 25% ink, "
                                f"wall 120 deg, periodic)",
-                   "nx": nx, "ny": ny, "diag_every": DIAG_EVERY, "tiling": "default"},
+                   "nx": nx, "ny": ny, "diag_every": DIAG_EVERY, "tiling": args.tiling or "default"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_collide_fused", "kernel_ms": round(kern_ms, 5),

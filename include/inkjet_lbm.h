@@ -206,8 +206,9 @@ ij_status ij_check(ij_sim *s, void *stream);
 ij_status ij_derived(const ij_sim *s, double out[8]);
 
 /* Tile shape of the fused collide-stream kernel: waves across x per
- * workgroup (1, 2 or 4) and rows per workgroup (>= 1).  0 keeps the
- * current value. */
+ * workgroup (1, 2 or 4) and rows per workgroup (1..1024); the default is
+ * 4 waves (256 columns) by 32 rows.  0 keeps the current value.  Results
+ * do not depend on the tile shape (bit for bit). */
 ij_status ij_set_tiling(ij_sim *s, int32_t waves_x, int32_t rows_per_block);
 
 #ifdef __cplusplus

@@ -51,7 +51,12 @@ struct ij_sim {
     int64_t t = 0;
     bool initialised = false;
     int64_t unstable_step = -1;
-    int waves_x = 4, rows_per_block = 64;
+    int waves_x = 4, rows_per_block = 32;
+    // rows of each strip the plain collide-stream path may take, and the
+    // tiles that hold the other rows (rebuilt with the wall or the tiling)
+    uint8_t* plain = nullptr;
+    int* gtiles = nullptr;
+    int n_gtiles = 0;
     std::string err;
 };
 
@@ -186,6 +191,8 @@ void fill_kparams(ij_sim* s)
     K.fb = 0.f;
 }
 
+ij_status build_plain(ij_sim* s);
+
 ij_status upload_wall(ij_sim* s)
 {
     // padded device copy and the list of solid nodes with a fluid neighbour
@@ -222,6 +229,62 @@ ij_status upload_wall(ij_sim* s)
         IJ_HIP(s, hipMemcpy(s->ghost, list.data(), list.size() * sizeof(int2), hipMemcpyHostToDevice));
     }
     s->initialised = false;
+    return build_plain(s);
+}
+
+// Plain rows: for strip k (columns [x0, x0 + w) with two halo columns each
+// side) row r is plain when rows r-1..r+1 hold no solid node in those
+// columns and, with open rows, 1 <= r <= ny-2.  Tiles (strip, block of rows)
+// that contain any other row go to the general launch.
+ij_status build_plain(ij_sim* s)
+{
+    const int nx = s->nx, ny = s->ny;
+    const int bw = 64 * s->waves_x;
+    const int n_strips = (nx + bw - 1) / bw;
+    const int n_rb = (ny + s->rows_per_block - 1) / s->rows_per_block;
+    const bool open = s->p.bc_y == IJ_BC_OPEN;
+    // rows with any solid node in a column window: per strip
+    std::vector<uint8_t> plain((size_t)n_strips * ny, 0);
+    std::vector<int> tiles;
+    for (int k = 0; k < n_strips; ++k) {
+        const int x0 = k * bw, w = std::min(bw, nx - x0);
+        std::vector<uint8_t> solid_row(ny, 0);
+        for (int y = 0; y < ny; ++y)
+            for (int c = x0 - 2; c < x0 + w + 2 && !solid_row[y]; ++c)
+                if (s->wall_host[(size_t)y * nx + ((c % nx) + nx) % nx] != 0) solid_row[y] = 1;
+        for (int y = 0; y < ny; ++y) {
+            bool ok = !(open && (y < 1 || y > ny - 2));
+            for (int dy = -1; dy <= 1 && ok; ++dy) {
+                int r = y + dy;
+                if (r < 0 || r >= ny) {
+                    if (open) { ok = false; break; }
+                    r = (r + ny) % ny;
+                }
+                if (solid_row[r]) ok = false;
+            }
+            plain[(size_t)k * ny + y] = ok ? 1 : 0;
+        }
+    }
+    // tiles are numbered row-block major: tile = block * n_strips + strip
+    for (int b = 0; b < n_rb; ++b)
+        for (int k = 0; k < n_strips; ++k) {
+            const int y0 = b * s->rows_per_block, y1 = std::min(ny, y0 + s->rows_per_block);
+            bool general = false;
+            for (int y = y0; y < y1 && !general; ++y) general = !plain[(size_t)k * ny + y];
+            if (general) tiles.push_back(b * n_strips + k);
+        }
+    if (s->plain) (void)hipFree(s->plain);
+    if (s->gtiles) (void)hipFree(s->gtiles);
+    s->plain = nullptr;
+    s->gtiles = nullptr;
+    if (hipMalloc(&s->plain, plain.size()) != hipSuccess) return fail(s, IJ_ERR_OOM, "plain-row table allocation failed");
+    IJ_HIP(s, hipMemcpy(s->plain, plain.data(), plain.size(), hipMemcpyHostToDevice));
+    s->n_gtiles = (int)tiles.size();
+    if (s->n_gtiles) {
+        if (hipMalloc(&s->gtiles, tiles.size() * sizeof(int)) != hipSuccess)
+            return fail(s, IJ_ERR_OOM, "tile list allocation failed");
+        IJ_HIP(s, hipMemcpy(s->gtiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     return IJ_OK;
 }
 
@@ -321,7 +384,6 @@ ij_status ij_create(const ij_params* p, ij_sim** out)
     s->wet_in = 2.0 * wetting_omega(p->theta_inner) * s->phi_star / p->width;
     s->wet_out = 2.0 * wetting_omega(p->theta_outer) * s->phi_star / p->width;
     if (s->p.force_rows == 0 && p->nozzle_w > 0) s->p.force_rows = p->nozzle_len;
-    s->waves_x = 1;
     fill_kparams(s);
 
     const size_t bytes = buffer_bytes(s->plane);
@@ -358,6 +420,8 @@ void ij_destroy(ij_sim* s)
     if (s->ghost) (void)hipFree(s->ghost);
     if (s->rows) (void)hipFree(s->rows);
     if (s->samples) (void)hipFree(s->samples);
+    if (s->plain) (void)hipFree(s->plain);
+    if (s->gtiles) (void)hipFree(s->gtiles);
     delete s;
 }
 
@@ -448,8 +512,8 @@ ij_status ij_step(ij_sim* s, int64_t nsteps, void* stream)
             if (r != IJ_OK) return r;
         }
         s->K.fb = (float)pulse_value(s->p, s->t);
-        hipError_t e = ij::launch_collide_fused(s->K, s->buf[s->cur], s->buf[1 - s->cur], s->wall, s->waves_x,
-                                                s->rows_per_block, st);
+        hipError_t e = ij::launch_collide_fused(s->K, s->buf[s->cur], s->buf[1 - s->cur], s->wall, s->plain,
+                                                s->gtiles, s->n_gtiles, s->waves_x, s->rows_per_block, st);
         if (e != hipSuccess) return hip_fail(s, e, "collide-stream kernel");
         s->cur = 1 - s->cur;
         s->t += 1;
@@ -614,10 +678,11 @@ ij_status ij_set_tiling(ij_sim* s, int32_t waves_x, int32_t rows_per_block)
     if (!s) return IJ_ERR_INVALID_ARG;
     if (waves_x != 0 && waves_x != 1 && waves_x != 2 && waves_x != 4)
         return fail(s, IJ_ERR_INVALID_ARG, "waves_x must be 1, 2 or 4");
-    if (rows_per_block < 0) return fail(s, IJ_ERR_INVALID_ARG, "rows_per_block must be >= 0");
+    if (rows_per_block < 0 || rows_per_block > 1024)
+        return fail(s, IJ_ERR_INVALID_ARG, "rows_per_block must lie in [0, 1024]");
     if (waves_x) s->waves_x = waves_x;
     if (rows_per_block) s->rows_per_block = rows_per_block;
-    return IJ_OK;
+    return build_plain(s);
 }
 
 }  // extern "C"

@@ -19,6 +19,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "lbm_core.h"
 
 namespace ij {
@@ -290,6 +292,62 @@ __device__ __forceinline__ void stream_one(const StreamCtx& c, float hv, float g
     }
 }
 
+// Streaming of a population that changes column (c_x != 0) inside one
+// wave, with aligned stores.  Push semantics are kept: the value v of node
+// (x, y) still lands in x + c_i, or bounces back into (x, y) when x + c_i is
+// solid, or is dropped beyond an open row; but the store into column x + c_i
+// is issued by the lane that owns that column, which receives the value vin
+// of its neighbour x - c_i (through LDS), so every row of a plane is written
+// by whole cache lines.  Only the lane at the wave edge pushes its value
+// across the edge itself.  For g, g_recv is the pre-collision g_I of the
+// receiving slot (the lane's own node, c_y = 0 for the g directions that
+// move in x), g_self the own g of the opposite direction (bounce-back) and
+// g_edge the pre-collision g_I of the node across the wave edge.
+struct ShiftCtx {
+    const KParams* P;
+    float* B;
+    int t, lane, wv, x, y;
+    bool active, own_fluid;
+};
+
+template <int I, bool IS_G, typename MaskRel, typename OpenFn>
+__device__ __forceinline__ void stream_shifted(const ShiftCtx& c, float v, float vin, float g_recv, float g_self,
+                                               float g_edge, MaskRel mask_rel, OpenFn open_fluid)
+{
+    constexpr int DX = Dir<I>::dx, DY = Dir<I>::dy, OPP = Dir<I>::opp;
+    const KParams& P = *c.P;
+    int ty = c.y + DY;
+    bool in_lat = true;
+    if (DY != 0 && (ty < 0 || ty >= P.ny)) {
+        if (P.bc_open) in_lat = false;
+        else ty = ty < 0 ? ty + P.ny : ty - P.ny;
+    }
+    const int pl = IS_G ? 9 + I : I;
+    auto put = [&](int plane_idx, int cyd, int wx, int wy, int dxo, float val) {
+        c.B[(size_t)plane_idx * P.plane + (unsigned)wy * P.pitch + wx] = val;
+        if (P.bc_open) {
+            if (cyd > 0 && wy == 1 && open_fluid(0, dxo)) c.B[(size_t)plane_idx * P.plane + wx] = val;
+            if (cyd < 0 && wy == P.ny - 2 && open_fluid(1, dxo))
+                c.B[(size_t)plane_idx * P.plane + (unsigned)(P.ny - 1) * P.pitch + wx] = val;
+        }
+    };
+    // receive: this lane's column at row y + DY, pushed from column x - DX
+    const int src_lane = c.lane - DX, src_t = c.t - DX;
+    const bool src_in_wave = src_lane >= 0 && src_lane < 64 && src_t >= 0 && src_t < c.wv;
+    if (c.active && in_lat && src_in_wave && mask_rel(0, -DX) == 0 && mask_rel(DY, 0) == 0)
+        put(pl, DY, c.x, ty, 0, IS_G ? vin + P.omq * g_recv : vin);
+    // own push: bounce-back, or across the wave edge
+    if (c.own_fluid && in_lat) {
+        const bool tgt_fluid = mask_rel(DY, DX) == 0;
+        const int dst_lane = c.lane + DX, dst_t = c.t + DX;
+        const bool dst_in_wave = dst_lane >= 0 && dst_lane < 64 && dst_t >= 0 && dst_t < c.wv;
+        if (!tgt_fluid)
+            put(IS_G ? 9 + OPP : OPP, -DY, c.x, c.y, 0, IS_G ? v + P.omq * g_self : v);
+        else if (!dst_in_wave)
+            put(pl, DY, wrapx(c.x + DX, P.nx), ty, DX, IS_G ? v + P.omq * g_edge : v);
+    }
+}
+
 // ------------------------------------------------------ reference path kernels
 
 // raw phi at fluid nodes into the phi field (solid entries untouched)
@@ -407,148 +465,187 @@ __global__ void k_collide_ref(KParams P, const float* __restrict__ A, float* __r
 //
 // One workgroup owns a strip of BW = 64*NW columns and a block of rows and
 // marches up the rows.  Per row it (1) forms raw phi of row r+2 (from g and
-// the g_0 remainder, loaded one iteration ahead) in an LDS ring with two
-// halo columns each side, (2) turns row r+1 into phi~ (wetting ghosts at
-// solid nodes), (3) collides row r (its distributions also loaded one
-// iteration ahead) with the nine-point stencil from LDS and streams it.  phi
-// never goes through HBM: per fluid node the kernel reads the 14
-// distributions and the 16-bit g_0 remainder once and writes them once.  The
-// pre-collision g of the destination (the (1-q) term of Eq. 8) comes from
-// the row registers or the LDS ring, never from memory.
-template <int NW>
+// the g_0 remainder) in an LDS ring with two halo columns each side, (2)
+// turns row r+1 into phi~ (wetting ghosts at solid nodes), (3) collides row
+// r with the nine-point stencil from LDS and streams it.  phi never goes
+// through HBM: per fluid node the kernel reads the 14 distributions and the
+// 16-bit g_0 remainder once and writes them once.
+//
+// Memory-level parallelism: the loads of a raw row and of a collide row are
+// issued two iterations before their use into two alternating register sets
+// (the loop is unrolled by two, so no register copies wait on them), and no
+// branch depends on a value still in flight: raw rows are loaded whatever
+// their mask and masked afterwards; the decision to load a collide row uses
+// masks and row flags already in LDS.
+//
+// Stores are aligned: a population that changes column is handed to the
+// lane that owns the destination column (a wave shift for rows without
+// solid nodes, LDS otherwise); only the wave-edge lanes store across the
+// edge.  Rows are "plain" when the geometry puts no solid node in rows
+// r-1..r+1 of the strip and its halo and no open row within reach (a static
+// per-(strip,row) table built on the host).  The PLAIN instantiation
+// collides and streams only plain rows, with a branch-free store sequence;
+// the other instantiation runs over the tiles that contain other rows and
+// collides only those, with every slot decided by the masks (bounce-back,
+// open-row copies).  Each fluid node is collided by exactly one of the two
+// launches.  Tiles are numbered row-block major, so that the workgroups
+// resident at one time cover whole rows of the planes.
+constexpr int kMaxRowsPerBlock = 1024;
+
+// The value held by lane - 1 (from_left) or lane + 1 (from_right) of the
+// wave (DPP wave shifts); the lane at the wave edge gets its own value back.
+__device__ __forceinline__ float from_left(float v)
+{
+    const int b = __float_as_int(v);
+    return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x138, 0xf, 0xf, false));   // wave_shr:1
+}
+__device__ __forceinline__ float from_right(float v)
+{
+    const int b = __float_as_int(v);
+    return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x130, 0xf, 0xf, false));   // wave_shl:1
+}
+
+template <int NW, bool PLAIN>
 __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const float* __restrict__ A,
                                                            float* __restrict__ B,
                                                            const uint8_t* __restrict__ wall,
+                                                           const uint8_t* __restrict__ plain_rows,
+                                                           const int* __restrict__ tile_list,
                                                            int rows_per_block, int n_strips,
                                                            int n_rowblocks)
 {
     constexpr int BW = 64 * NW;
-    constexpr int RING = 8;
+    // raw rows rr-3..rr are in use while row rr is processed; the last
+    // reader of a slot finishes before the barrier that ends the row
+    constexpr int RING = 4;
     __shared__ double s_raw[RING][BW + 4];
     __shared__ uint8_t s_m[RING][BW + 4];
-    __shared__ float s_g1[RING][BW + 4];  // g_1 and g_3 of each raw row: the
-    __shared__ float s_g3[RING][BW + 4];  // (1-q) terms of the x-neighbours
+    __shared__ float s_g[5][RING][BW + 4];   // pre-collision g of each raw row
+    __shared__ uint16_t s_lo[RING][BW];      // g_0 remainder bits of each raw row
     __shared__ double s_pt[4][BW + 2];
+    __shared__ float s_out[PLAIN ? 1 : 12][BW + 2];   // post-collision f_1..f_8, h_1..h_4 of the row
+    __shared__ uint8_t s_mine[kMaxRowsPerBlock];      // rows of the block this launch collides
 
-    // consecutive tiles of a strip are vertical neighbours; keep runs of them
-    // on one XCD (workgroups are dealt round-robin over the 8 XCDs)
-    const int ntiles = n_strips * n_rowblocks;
-    int tile = blockIdx.x;
-    if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
-    const int strip = tile / n_rowblocks;
-    const int rb = tile - strip * n_rowblocks;
+    int tile;
+    if (PLAIN) {
+        // keep runs of consecutive tiles on one XCD (workgroups are dealt
+        // round-robin over the 8 XCDs, each with its own L2)
+        const int ntiles = n_strips * n_rowblocks;
+        tile = blockIdx.x;
+        if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+    } else {
+        tile = tile_list[blockIdx.x];
+    }
+    const int rb = tile / n_strips;
+    const int strip = tile - rb * n_strips;
     const int x0 = strip * BW;
     const int wv = min(BW, P.nx - x0);
     const int y0 = rb * rows_per_block;
     const int y1 = min(P.ny, y0 + rows_per_block);
     const int t = threadIdx.x;
+    const int lane = t & 63;
     const bool active = t < wv;
     const int x = x0 + t;
-    const int hx = t < 2 ? x0 - 2 + t : x0 + wv + (t - 2);   // halo column of threads 0..3
-    const int hidx = t < 2 ? t : wv + 2 + (t - 2);
-    const int hxw = wrapx(hx, P.nx);
+    const int hidx = t < 2 ? t : wv + 2 + (t - 2);   // LDS column of the halo of threads 0..3
 
-    const float* Ag = A + (size_t)9 * P.plane;
+    for (int i = t; i < y1 - y0; i += BW)
+        s_mine[i] = (plain_rows[(size_t)strip * P.ny + y0 + i] != 0) == PLAIN;
+
+    // plane bases (uniform) and 32-bit byte offsets
+    const size_t pl = P.plane;
+    const float* Af[9];
+    float* Bf[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) { Af[i] = A + i * pl; Bf[i] = B + i * pl; }
+    const float* Ag[5];
+    float* Bg[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) { Ag[i] = A + (9 + i) * pl; Bg[i] = B + (9 + i) * pl; }
     const uint16_t* Alo = lo_plane(A, P);
+    uint16_t* Blo = lo_plane(B, P);
+    auto boff = [&](int xx, int yy) -> unsigned { return ((unsigned)yy * (unsigned)P.pitch + (unsigned)xx) << 2; };
+    auto ldf = [](const float* base, unsigned bo) { return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + bo); };
+    auto stf = [](float* base, unsigned bo, float v) { *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + bo) = v; };
 
-    // raw-row registers: row rr (newest), rr-1, rr-2 (= collide row)
-    float g2[5], g1[5], gc[5], lo2 = 0.f, lo1 = 0.f, loc = 0.f, g4prev = 0.f;
-    uint8_t m2 = 3, m1 = 3;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) { g2[i] = 0.f; g1[i] = 0.f; gc[i] = 0.f; }
-    // loads issued one iteration ahead
-    float pg[5], plo = 0.f, hg[5], hlo = 0.f, pf[9];
-    uint8_t pm = 3, hm = 3;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) pf[i] = 0.f;
+    // two register sets for loads in flight: raw rows (g, remainder bits,
+    // mask; halo columns) and collide rows (f)
+    float rg[2][5], hg[2][5], rf[2][9];
+    uint16_t rlo[2], hlo[2];
+    uint8_t rm[2], hm[2];
+    bool ron[2];
+    // every lane loads at an in-bounds column: lanes past the lattice edge
+    // reuse the last column, and every lane loads the halo column of lane
+    // t % 4 (only lanes 0..3 keep it)
+    const int xc = active ? x : P.nx - 1;
+    const int hq = t & 3;
+    const int hx = wrapx(hq < 2 ? x0 - 2 + hq : x0 + wv + (hq - 2), P.nx);
 
-    auto fetch_raw = [&](int rr) {
+    // Loads are issued without any branch around them, at in-bounds
+    // addresses, so that the number of memory operations issued after a
+    // fetch is known at its use and the wait there is partial.
+    auto fetch_raw = [&](int rr, float (&g)[5], uint16_t& lo, uint8_t& m, float (&gh)[5], uint16_t& loh,
+                         uint8_t& mh, bool& on) {
         int ry = rr;
-        bool on = true;
+        on = true;
         if (ry < 0 || ry >= P.ny) {
-            if (P.bc_open) on = false;
+            if (P.bc_open) { on = false; ry = 0; }
             else ry = ry < 0 ? ry + P.ny : ry - P.ny;
         }
-        pm = 3;
+        const unsigned k = (unsigned)ry * P.pitch + xc;
+        const unsigned kh = (unsigned)ry * P.pitch + hx;
+        m = wall[k];
+        mh = wall[kh];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) pg[i] = 0.f;
-        plo = 0.f;
-        if (on && active) {
-            const unsigned k = (unsigned)ry * P.pitch + x;
-            pm = wall[k];
-            if (pm == 0) {
+        for (int i = 0; i < 5; ++i) g[i] = ldf(Ag[i], k << 2);
 #pragma unroll
-                for (int i = 0; i < 5; ++i) pg[i] = Ag[(size_t)i * P.plane + k];
-                plo = bf16_to_float(Alo[k]);
-            }
-        }
-        hm = 3;
-#pragma unroll
-        for (int i = 0; i < 5; ++i) hg[i] = 0.f;
-        hlo = 0.f;
-        if (on && t < 4) {
-            const unsigned k = (unsigned)ry * P.pitch + hxw;
-            hm = wall[k];
-            if (hm == 0) {
-#pragma unroll
-                for (int i = 0; i < 5; ++i) hg[i] = Ag[(size_t)i * P.plane + k];
-                hlo = bf16_to_float(Alo[k]);
-            }
-        }
+        for (int i = 0; i < 5; ++i) gh[i] = ldf(Ag[i], kh << 2);
+        lo = Alo[k];
+        loh = Alo[kh];
     };
 
-    const int nk = (y1 - y0) + 4;
-    fetch_raw(y0 - 2);
-    for (int kk = 0; kk < nk; ++kk) {
+    // rows y0-2 .. y1+1 pass through the ring; the count is rounded up to
+    // an even number (the extra iteration collides nothing)
+    const int nk = ((y1 - y0) + 5) & ~1;
+
+    // iteration kk: raw row rr = y0 - 2 + kk, phi~ row rr - 1, collide row
+    // rc = rr - 2; register set S = kk % 2
+    auto body = [&](auto Sc, int kk) {
+        constexpr int S = decltype(Sc)::value;
         const int rr = y0 - 2 + kk;
         const int rc = rr - 2;
         const int slot = rr & (RING - 1);
-        g4prev = gc[4];
+
+        // (1) raw row rr into the LDS ring (non-fluid entries zeroed)
+        {
+            const uint8_t m = ron[S] && active ? rm[S] : 3;
+            if (active) {
+                const bool fl = m == 0;
+                s_m[slot][t + 2] = m;
+                s_raw[slot][t + 2] =
+                    fl ? phi_of(rg[S][0], rg[S][1], rg[S][2], rg[S][3], rg[S][4], bf16_to_float(rlo[S])) : 0.0;
 #pragma unroll
-        for (int i = 0; i < 5; ++i) { gc[i] = g1[i]; g1[i] = g2[i]; g2[i] = pg[i]; }
-        loc = lo1;
-        lo1 = lo2;
-        lo2 = plo;
-        const uint8_t mc = m1;  // mask of the collide row rc
-        m1 = m2;
-        m2 = pm;
-        const float hg1 = hg[1], hg3 = hg[3];
-        const double hraw = hm == 0 ? phi_of(hg[0], hg[1], hg[2], hg[3], hg[4], hlo) : 0.0;
-        const uint8_t hmm = hm;
-        float fc[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) fc[i] = pf[i];
-        // issue the next iteration's loads before working on this one: the
-        // raw row rr+1 and the distributions of the next collide row rc+1,
-        // whose mask m1 is already known
-        if (kk + 1 < nk) {
-            fetch_raw(rr + 1);
-            if (rc + 1 >= y0 && rc + 1 < y1 && active && m1 == 0) {
-                const unsigned k = (unsigned)(rc + 1) * P.pitch + x;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) pf[i] = A[(size_t)i * P.plane + k];
+                for (int i = 0; i < 5; ++i) s_g[i][slot][t + 2] = fl ? rg[S][i] : 0.f;
+                s_lo[slot][t] = fl ? rlo[S] : (uint16_t)0;
+            }
+            if (t < 4) {
+                const uint8_t mh = ron[S] ? hm[S] : 3;
+                const bool fl = mh == 0;
+                s_m[slot][hidx] = mh;
+                s_raw[slot][hidx] =
+                    fl ? phi_of(hg[S][0], hg[S][1], hg[S][2], hg[S][3], hg[S][4], bf16_to_float(hlo[S])) : 0.0;
+                s_g[1][slot][hidx] = fl ? hg[S][1] : 0.f;
+                s_g[3][slot][hidx] = fl ? hg[S][3] : 0.f;
             }
         }
-
-        // (1) raw phi and mask of row rr
-        if (active) {
-            s_raw[slot][t + 2] = m2 == 0 ? phi_of(g2[0], g2[1], g2[2], g2[3], g2[4], lo2) : 0.0;
-            s_m[slot][t + 2] = m2;
-            s_g1[slot][t + 2] = g2[1];
-            s_g3[slot][t + 2] = g2[3];
-        }
-        if (t < 4) {
-            s_raw[slot][hidx] = hraw;
-            s_m[slot][hidx] = hmm;
-            s_g1[slot][hidx] = hg1;
-            s_g3[slot][hidx] = hg3;
-        }
+        // the raw row two iterations ahead reuses set S (past the end of
+        // the block the loads are redundant and masked off)
+        fetch_raw(rr + 2, rg[S], rlo[S], rm[S], hg[S], hlo[S], hm[S], ron[S]);
         __syncthreads();
 
         // (2) phi~ of row rr-1
         if (kk >= 1) {
-            const int rg = rr - 1;
-            const int sc = rg & (RING - 1), sn = (rg + 1) & (RING - 1), ss = (rg - 1) & (RING - 1);
+            const int rgw = rr - 1;
+            const int sc = rgw & (RING - 1), sn = (rgw + 1) & (RING - 1), ss = (rgw - 1) & (RING - 1);
             auto phit = [&](int j) -> double {
                 const uint8_t m0 = s_m[sc][j];
                 if (m0 == 0) return s_raw[sc][j];
@@ -563,64 +660,154 @@ __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const floa
                 mm[5] = s_m[sn][j - 1]; v[5] = s_raw[sn][j - 1];
                 mm[6] = s_m[ss][j - 1]; v[6] = s_raw[ss][j - 1];
                 mm[7] = s_m[ss][j + 1]; v[7] = s_raw[ss][j + 1];
-                return ghost_value(v, mm, P.wet[m0]);
+                return ghost_value(v, mm, m0 == 1 ? P.wet[1] : P.wet[2]);   // no indexed kernarg load
             };
-            if (active) s_pt[rg & 3][t + 1] = phit(t + 2);
+            if (active) s_pt[rgw & 3][t + 1] = phit(t + 2);
             if (t < 2) {
                 const int j = t == 0 ? 1 : wv + 2;
-                s_pt[rg & 3][t == 0 ? 0 : wv + 1] = phit(j);
+                s_pt[rgw & 3][t == 0 ? 0 : wv + 1] = phit(j);
             }
         }
         __syncthreads();
 
-        // (3) collide and stream row rr-2
-        if (kk >= 2 && rc >= y0 && active && mc == 0) {
-            const int rn = (P.bc_open && rc == P.ny - 1) ? rc : rc + 1;
-            const int rs = (P.bc_open && rc == 0) ? rc : rc - 1;
-            const int pc = rc & 3, pn = rn & 3, ps = rs & 3;
-            const int j = t + 1;
-            double st[9];
-            st[0] = s_pt[pc][j];
-            st[1] = s_pt[pc][j + 1];
-            st[2] = s_pt[pn][j];
-            st[3] = s_pt[pc][j - 1];
-            st[4] = s_pt[ps][j];
-            st[5] = s_pt[pn][j + 1];
-            st[6] = s_pt[pn][j - 1];
-            st[7] = s_pt[ps][j - 1];
-            st[8] = s_pt[ps][j + 1];
-            float fs[9], h[5], g0h;
-            uint16_t g0l;
-            Macro mac;
-            node_collide(P, fc, gc, loc, st, rc < P.force_rows ? P.fb : 0.f, fs, h, g0h, g0l, mac);
-
-            const unsigned own = (unsigned)rc * P.pitch + x;
-            B[own] = fs[0];
-            B[(size_t)9 * P.plane + own] = g0h;
-            lo_plane(B, P)[own] = g0l;
-            const StreamCtx c{&P, B, x, rc, own};
-            const int jm = t + 2;
+        // (3) collide and stream row rc (the condition is uniform over the
+        // workgroup: every lane reaches the barriers below)
+        if (kk >= 4 && rc < y1 && s_mine[rc - y0]) {
+            const int jm = t + 2, jo = t + 1;
             const int sc = rc & (RING - 1), sn = (rc + 1) & (RING - 1), ss = (rc - 1) & (RING - 1);
-            // rows 0 and ny-1 are in the ring whenever a copy into them occurs
-            auto open_fluid = [&](int top, int dx) {
-                const int row = top ? P.ny - 1 : 0;
-                return s_m[row & (RING - 1)][jm + dx] == 0;
-            };
-#define IJ_M(SLOT, DXX) [&]() { return s_m[SLOT][jm + (DXX)]; }
-            stream_one<1, false>(c, fs[1], 0.f, 0.f, IJ_M(sc, 1), open_fluid);
-            stream_one<2, false>(c, fs[2], 0.f, 0.f, IJ_M(sn, 0), open_fluid);
-            stream_one<3, false>(c, fs[3], 0.f, 0.f, IJ_M(sc, -1), open_fluid);
-            stream_one<4, false>(c, fs[4], 0.f, 0.f, IJ_M(ss, 0), open_fluid);
-            stream_one<5, false>(c, fs[5], 0.f, 0.f, IJ_M(sn, 1), open_fluid);
-            stream_one<6, false>(c, fs[6], 0.f, 0.f, IJ_M(sn, -1), open_fluid);
-            stream_one<7, false>(c, fs[7], 0.f, 0.f, IJ_M(ss, -1), open_fluid);
-            stream_one<8, false>(c, fs[8], 0.f, 0.f, IJ_M(ss, 1), open_fluid);
-            stream_one<1, true>(c, h[1], s_g1[sc][jm + 1], gc[3], IJ_M(sc, 1), open_fluid);
-            stream_one<2, true>(c, h[2], g1[2], gc[4], IJ_M(sn, 0), open_fluid);
-            stream_one<3, true>(c, h[3], s_g3[sc][jm - 1], gc[1], IJ_M(sc, -1), open_fluid);
-            stream_one<4, true>(c, h[4], g4prev, gc[2], IJ_M(ss, 0), open_fluid);
-#undef IJ_M
+            const bool own_fluid = active && s_m[sc][jm] == 0;
+            float fs[9], h[5];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fs[i] = 0.f;
+#pragma unroll
+            for (int i = 0; i < 5; ++i) h[i] = 0.f;
+            if (own_fluid) {
+                const int rn = (P.bc_open && rc == P.ny - 1) ? rc : rc + 1;
+                const int rs = (P.bc_open && rc == 0) ? rc : rc - 1;
+                const int pc = rc & 3, pn = rn & 3, ps = rs & 3;
+                double st[9];
+                st[0] = s_pt[pc][jo];
+                st[1] = s_pt[pc][jo + 1];
+                st[2] = s_pt[pn][jo];
+                st[3] = s_pt[pc][jo - 1];
+                st[4] = s_pt[ps][jo];
+                st[5] = s_pt[pn][jo + 1];
+                st[6] = s_pt[pn][jo - 1];
+                st[7] = s_pt[ps][jo - 1];
+                st[8] = s_pt[ps][jo + 1];
+                float gcur[5];
+#pragma unroll
+                for (int i = 0; i < 5; ++i) gcur[i] = s_g[i][sc][jm];
+                float g0h;
+                uint16_t g0l;
+                Macro mac;
+                node_collide(P, rf[S], gcur, bf16_to_float(s_lo[sc][t]), st, rc < P.force_rows ? P.fb : 0.f, fs,
+                             h, g0h, g0l, mac);
+                const unsigned bo = boff(x, rc);
+                stf(Bf[0], bo, fs[0]);
+                stf(Bg[0], bo, g0h);
+                Blo[(unsigned)rc * P.pitch + x] = g0l;
+                if (!PLAIN) {
+#pragma unroll
+                    for (int i = 1; i < 9; ++i) s_out[i - 1][jo] = fs[i];
+#pragma unroll
+                    for (int i = 1; i < 5; ++i) s_out[7 + i][jo] = h[i];
+                }
+            }
+            if (PLAIN) {
+                // every node of rows rc-1..rc+1 is fluid; the populations
+                // moving in x come from the neighbouring lanes
+                const float l1 = from_left(fs[1]), l5 = from_left(fs[5]), l8 = from_left(fs[8]);
+                const float lh1 = from_left(h[1]);
+                const float r3 = from_right(fs[3]), r6 = from_right(fs[6]), r7 = from_right(fs[7]);
+                const float rh3 = from_right(h[3]);
+                if (active) {
+                    const int yn = rc + 1 >= P.ny ? rc + 1 - P.ny : rc + 1;   // periodic wrap
+                    const int ys = rc == 0 ? P.ny - 1 : rc - 1;
+                    const unsigned bc = boff(x, rc), bn = boff(x, yn), bs = boff(x, ys);
+                    stf(Bf[2], bn, fs[2]);
+                    stf(Bf[4], bs, fs[4]);
+                    stf(Bg[2], bn, h[2] + P.omq * s_g[2][sn][jm]);
+                    stf(Bg[4], bs, h[4] + P.omq * s_g[4][ss][jm]);
+                    if (lane >= 1) {                       // pusher x-1 is in this wave
+                        stf(Bf[1], bc, l1);
+                        stf(Bf[5], bn, l5);
+                        stf(Bf[8], bs, l8);
+                        stf(Bg[1], bc, lh1 + P.omq * s_g[1][sc][jm]);
+                    }
+                    if (lane < 63 && t + 1 < wv) {         // pusher x+1 is in this wave
+                        stf(Bf[3], bc, r3);
+                        stf(Bf[6], bn, r6);
+                        stf(Bf[7], bs, r7);
+                        stf(Bg[3], bc, rh3 + P.omq * s_g[3][sc][jm]);
+                    }
+                    // the lanes at the wave edges store across them
+                    if (lane == 63 || t + 1 >= wv) {
+                        const int xe = wrapx(x + 1, P.nx);
+                        stf(Bf[1], boff(xe, rc), fs[1]);
+                        stf(Bf[5], boff(xe, yn), fs[5]);
+                        stf(Bf[8], boff(xe, ys), fs[8]);
+                        stf(Bg[1], boff(xe, rc), h[1] + P.omq * s_g[1][sc][jm + 1]);
+                    }
+                    if (lane == 0) {
+                        const int xw = wrapx(x - 1, P.nx);
+                        stf(Bf[3], boff(xw, rc), fs[3]);
+                        stf(Bf[6], boff(xw, yn), fs[6]);
+                        stf(Bf[7], boff(xw, ys), fs[7]);
+                        stf(Bg[3], boff(xw, rc), h[3] + P.omq * s_g[3][sc][jm - 1]);
+                    }
+                }
+            } else {
+                __syncthreads();
+                // masks decide every slot
+                auto open_fluid = [&](int top, int dx) {
+                    // rows 0 and ny-1 are in the ring whenever a copy into them occurs
+                    const int row = top ? P.ny - 1 : 0;
+                    return s_m[row & (RING - 1)][jm + dx] == 0;
+                };
+                auto mask_rel = [&](int dy, int dx) { return s_m[(rc + dy) & (RING - 1)][jm + dx]; };
+                if (own_fluid) {
+                    const StreamCtx c{&P, B, x, rc, (unsigned)rc * P.pitch + x};
+                    stream_one<2, false>(c, fs[2], 0.f, 0.f, [&]() { return mask_rel(1, 0); }, open_fluid);
+                    stream_one<4, false>(c, fs[4], 0.f, 0.f, [&]() { return mask_rel(-1, 0); }, open_fluid);
+                    stream_one<2, true>(c, h[2], s_g[2][sn][jm], s_g[4][sc][jm], [&]() { return mask_rel(1, 0); },
+                                        open_fluid);
+                    stream_one<4, true>(c, h[4], s_g[4][ss][jm], s_g[2][sc][jm], [&]() { return mask_rel(-1, 0); },
+                                        open_fluid);
+                }
+                const ShiftCtx sx{&P, B, t, lane, wv, x, rc, active, own_fluid};
+                stream_shifted<1, false>(sx, fs[1], s_out[0][jo - 1], 0.f, 0.f, 0.f, mask_rel, open_fluid);
+                stream_shifted<3, false>(sx, fs[3], s_out[2][jo + 1], 0.f, 0.f, 0.f, mask_rel, open_fluid);
+                stream_shifted<5, false>(sx, fs[5], s_out[4][jo - 1], 0.f, 0.f, 0.f, mask_rel, open_fluid);
+                stream_shifted<6, false>(sx, fs[6], s_out[5][jo + 1], 0.f, 0.f, 0.f, mask_rel, open_fluid);
+                stream_shifted<7, false>(sx, fs[7], s_out[6][jo + 1], 0.f, 0.f, 0.f, mask_rel, open_fluid);
+                stream_shifted<8, false>(sx, fs[8], s_out[7][jo - 1], 0.f, 0.f, 0.f, mask_rel, open_fluid);
+                stream_shifted<1, true>(sx, h[1], s_out[8][jo - 1], s_g[1][sc][jm], s_g[3][sc][jm],
+                                        s_g[1][sc][jm + 1], mask_rel, open_fluid);
+                stream_shifted<3, true>(sx, h[3], s_out[10][jo + 1], s_g[3][sc][jm], s_g[1][sc][jm],
+                                        s_g[3][sc][jm - 1], mask_rel, open_fluid);
+            }
         }
+        // the distributions of collide row rc + 2 into set S; rows this
+        // launch does not collide load row y0 again instead (a cache hit)
+        {
+            const int rf2 = rc + 2;
+            const bool need = rf2 >= y0 && rf2 < y1 && s_mine[rf2 - y0];
+            const unsigned bo = boff(xc, need ? rf2 : y0);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) rf[S][i] = ldf(Af[i], bo);
+        }
+        if (NW > 1) __syncthreads();   // the ring slot of row rr - 3 is reused next
+    };
+
+#pragma unroll
+    for (int i = 0; i < 9; ++i) rf[0][i] = rf[1][i] = 0.f;
+    fetch_raw(y0 - 2, rg[0], rlo[0], rm[0], hg[0], hlo[0], hm[0], ron[0]);
+    fetch_raw(y0 - 1, rg[1], rlo[1], rm[1], hg[1], hlo[1], hm[1], ron[1]);
+    __syncthreads();   // s_mine
+    for (int kk = 0; kk < nk; kk += 2) {
+        body(std::integral_constant<int, 0>{}, kk);
+        body(std::integral_constant<int, 1>{}, kk + 1);
     }
 }
 
@@ -974,25 +1161,27 @@ hipError_t launch_collide_ref(const KParams& P, const float* A, float* B, const 
 }
 
 hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, const uint8_t* wall,
+                                const uint8_t* plain_rows, const int* general_tiles, int n_general_tiles,
                                 int waves_x, int rows_per_block, hipStream_t st)
 {
     const int bw = 64 * waves_x;
     const int n_strips = (P.nx + bw - 1) / bw;
     const int n_rb = (P.ny + rows_per_block - 1) / rows_per_block;
-    const dim3 grid(n_strips * n_rb);
+    const dim3 grid(n_strips * n_rb), ggrid(n_general_tiles);
+#define IJ_LAUNCH(NWV)                                                                                      \
+    hipLaunchKernelGGL((k_collide_fused<NWV, true>), grid, dim3(64 * NWV), 0, st, P, A, B, wall, plain_rows,  \
+                       general_tiles, rows_per_block, n_strips, n_rb);                                      \
+    if (n_general_tiles > 0)                                                                                \
+        hipLaunchKernelGGL((k_collide_fused<NWV, false>), ggrid, dim3(64 * NWV), 0, st, P, A, B, wall,       \
+                           plain_rows, general_tiles, rows_per_block, n_strips, n_rb);
     switch (waves_x) {
-    case 1:
-        hipLaunchKernelGGL(k_collide_fused<1>, grid, dim3(64), 0, st, P, A, B, wall, rows_per_block, n_strips, n_rb);
-        break;
-    case 2:
-        hipLaunchKernelGGL(k_collide_fused<2>, grid, dim3(128), 0, st, P, A, B, wall, rows_per_block, n_strips, n_rb);
-        break;
-    case 4:
-        hipLaunchKernelGGL(k_collide_fused<4>, grid, dim3(256), 0, st, P, A, B, wall, rows_per_block, n_strips, n_rb);
-        break;
+    case 1: IJ_LAUNCH(1) break;
+    case 2: IJ_LAUNCH(2) break;
+    case 4: IJ_LAUNCH(4) break;
     default:
         return hipErrorInvalidValue;
     }
+#undef IJ_LAUNCH
     return hipGetLastError();
 }
 
