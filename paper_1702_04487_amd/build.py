@@ -1,4 +1,5 @@
-"""Build the HIP library (``libinkjet_lbm.so``) in-tree for gfx950."""
+"""Build the HIP library (``libinkjet_lbm.so``) and the copy calibration
+program (``bin/copy_calib``) in-tree for gfx950."""
 from __future__ import annotations
 
 import os
@@ -9,6 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libinkjet_lbm.so")
 SOURCES = [os.path.join(CSRC, "lbm_core.hip"), os.path.join(CSRC, "ij_api.cpp")]
+CALIB = os.path.join(HERE, "bin", "copy_calib")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -packed-fp32-ops: no v_pk_*_f32 (their forms are avoided on this target);
@@ -19,9 +21,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=o
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-shared", "-o", tmp, *SOURCES]
+def _hipcc(args, verbose):
+    cmd = [HIPCC, *FLAGS, *args]
     if verbose:
         print(" ".join(cmd))
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -31,7 +32,15 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed:\n{msg}")
     if verbose and msg.strip():
         print(msg)
+
+
+def build(verbose: bool = False) -> str:
+    tmp = LIB + ".tmp"
+    _hipcc(["-shared", "-o", tmp, *SOURCES], verbose)
     os.replace(tmp, LIB)
+    os.makedirs(os.path.dirname(CALIB), exist_ok=True)
+    _hipcc(["-o", CALIB + ".tmp", os.path.join(CSRC, "copy_calib.hip")], verbose)
+    os.replace(CALIB + ".tmp", CALIB)
     return LIB
 
 

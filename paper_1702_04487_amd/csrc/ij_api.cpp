@@ -22,6 +22,7 @@ thread_local std::string g_create_error;
 
 constexpr int kPitchAlign = 64;  // floats: 256-byte rows
 constexpr int64_t kSampleCap = 4096;
+constexpr int kGeneralRows = 4;   // rows per tile of the launch over rows next to solid nodes
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -241,7 +242,6 @@ ij_status build_plain(ij_sim* s)
     const int nx = s->nx, ny = s->ny;
     const int bw = 64 * s->waves_x;
     const int n_strips = (nx + bw - 1) / bw;
-    const int n_rb = (ny + s->rows_per_block - 1) / s->rows_per_block;
     const bool open = s->p.bc_y == IJ_BC_OPEN;
     // rows with any solid node in a column window: per strip
     std::vector<uint8_t> plain((size_t)n_strips * ny, 0);
@@ -265,10 +265,12 @@ ij_status build_plain(ij_sim* s)
             plain[(size_t)k * ny + y] = ok ? 1 : 0;
         }
     }
-    // tiles are numbered row-block major: tile = block * n_strips + strip
-    for (int b = 0; b < n_rb; ++b)
+    // general tiles are short (kGeneralRows rows: few rows to collide, many
+    // workgroups) and numbered row-block major: tile = block * n_strips + strip
+    const int n_rb_g = (ny + kGeneralRows - 1) / kGeneralRows;
+    for (int b = 0; b < n_rb_g; ++b)
         for (int k = 0; k < n_strips; ++k) {
-            const int y0 = b * s->rows_per_block, y1 = std::min(ny, y0 + s->rows_per_block);
+            const int y0 = b * kGeneralRows, y1 = std::min(ny, y0 + kGeneralRows);
             bool general = false;
             for (int y = y0; y < y1 && !general; ++y) general = !plain[(size_t)k * ny + y];
             if (general) tiles.push_back(b * n_strips + k);
@@ -513,7 +515,8 @@ ij_status ij_step(ij_sim* s, int64_t nsteps, void* stream)
         }
         s->K.fb = (float)pulse_value(s->p, s->t);
         hipError_t e = ij::launch_collide_fused(s->K, s->buf[s->cur], s->buf[1 - s->cur], s->wall, s->plain,
-                                                s->gtiles, s->n_gtiles, s->waves_x, s->rows_per_block, st);
+                                                s->gtiles, s->n_gtiles, s->waves_x, s->rows_per_block, kGeneralRows,
+                                                st);
         if (e != hipSuccess) return hip_fail(s, e, "collide-stream kernel");
         s->cur = 1 - s->cur;
         s->t += 1;

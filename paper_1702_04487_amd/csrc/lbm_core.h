@@ -46,10 +46,12 @@ hipError_t launch_phi_ghost(const KParams& P, const float* A, const uint8_t* wal
 hipError_t launch_collide_ref(const KParams& P, const float* A, float* B, const uint8_t* wall,
                               const double* phi, hipStream_t st);
 // plain_rows: [n_strips][ny] bytes, 1 where the row of the strip is plain
-// (see the kernel); general_tiles: indices of the tiles holding other rows.
+// (see the kernel).  The plain launch covers every tile of rows_per_block
+// rows; general_tiles lists the tiles of rows_general rows (numbered
+// block * n_strips + strip) that hold other rows.
 hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, const uint8_t* wall,
                                 const uint8_t* plain_rows, const int* general_tiles, int n_general_tiles,
-                                int waves_x, int rows_per_block, hipStream_t st);
+                                int waves_x, int rows_per_block, int rows_general, hipStream_t st);
 hipError_t launch_init(const KParams& P, float* A, const uint8_t* wall, double* phi, const float* src,
                        int from_distance, const float* ux, const float* uy, const int2* ghost_list,
                        int n_ghost, hipStream_t st);

@@ -637,9 +637,9 @@ __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const floa
                 s_g[3][slot][hidx] = fl ? hg[S][3] : 0.f;
             }
         }
-        // the raw row two iterations ahead reuses set S (past the end of
-        // the block the loads are redundant and masked off)
-        fetch_raw(rr + 2, rg[S], rlo[S], rm[S], hg[S], hlo[S], hm[S], ron[S]);
+        // the raw row two iterations ahead reuses set S (past the last row
+        // the block needs, the loads repeat that row: cache hits, unused)
+        fetch_raw(min(rr + 2, y1 + 1), rg[S], rlo[S], rm[S], hg[S], hlo[S], hm[S], ron[S]);
         __syncthreads();
 
         // (2) phi~ of row rr-1
@@ -707,14 +707,14 @@ __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const floa
                 stf(Bf[0], bo, fs[0]);
                 stf(Bg[0], bo, g0h);
                 Blo[(unsigned)rc * P.pitch + x] = g0l;
-                if (!PLAIN) {
+                if constexpr (!PLAIN) {
 #pragma unroll
                     for (int i = 1; i < 9; ++i) s_out[i - 1][jo] = fs[i];
 #pragma unroll
                     for (int i = 1; i < 5; ++i) s_out[7 + i][jo] = h[i];
                 }
             }
-            if (PLAIN) {
+            if constexpr (PLAIN) {
                 // every node of rows rc-1..rc+1 is fluid; the populations
                 // moving in x come from the neighbouring lanes
                 const float l1 = from_left(fs[1]), l5 = from_left(fs[5]), l8 = from_left(fs[8]);
@@ -788,12 +788,13 @@ __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const floa
                                         s_g[3][sc][jm - 1], mask_rel, open_fluid);
             }
         }
-        // the distributions of collide row rc + 2 into set S; rows this
-        // launch does not collide load row y0 again instead (a cache hit)
+        // the distributions of collide row rc + 2 into set S; for rows this
+        // launch does not collide the loads go to a row of the block that is
+        // (or is about to be) in the cache, and are unused
         {
             const int rf2 = rc + 2;
-            const bool need = rf2 >= y0 && rf2 < y1 && s_mine[rf2 - y0];
-            const unsigned bo = boff(xc, need ? rf2 : y0);
+            const int rcl = min(max(rf2, y0), y1 - 1);
+            const unsigned bo = boff(xc, rcl);
 #pragma unroll
             for (int i = 0; i < 9; ++i) rf[S][i] = ldf(Af[i], bo);
         }
@@ -1162,18 +1163,22 @@ hipError_t launch_collide_ref(const KParams& P, const float* A, float* B, const 
 
 hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, const uint8_t* wall,
                                 const uint8_t* plain_rows, const int* general_tiles, int n_general_tiles,
-                                int waves_x, int rows_per_block, hipStream_t st)
+                                int waves_x, int rows_per_block, int rows_general, hipStream_t st)
 {
+    if (rows_per_block < 1 || rows_per_block > kMaxRowsPerBlock || rows_general < 1 ||
+        rows_general > kMaxRowsPerBlock)
+        return hipErrorInvalidValue;
     const int bw = 64 * waves_x;
     const int n_strips = (P.nx + bw - 1) / bw;
     const int n_rb = (P.ny + rows_per_block - 1) / rows_per_block;
+    const int n_rb_g = (P.ny + rows_general - 1) / rows_general;
     const dim3 grid(n_strips * n_rb), ggrid(n_general_tiles);
 #define IJ_LAUNCH(NWV)                                                                                      \
     hipLaunchKernelGGL((k_collide_fused<NWV, true>), grid, dim3(64 * NWV), 0, st, P, A, B, wall, plain_rows,  \
                        general_tiles, rows_per_block, n_strips, n_rb);                                      \
     if (n_general_tiles > 0)                                                                                \
         hipLaunchKernelGGL((k_collide_fused<NWV, false>), ggrid, dim3(64 * NWV), 0, st, P, A, B, wall,       \
-                           plain_rows, general_tiles, rows_per_block, n_strips, n_rb);
+                           plain_rows, general_tiles, rows_general, n_strips, n_rb_g);
     switch (waves_x) {
     case 1: IJ_LAUNCH(1) break;
     case 2: IJ_LAUNCH(2) break;
