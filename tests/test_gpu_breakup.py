@@ -1,0 +1,55 @@
+"""Breakup step, drop velocity, drop volume and the satellite flag of the
+GPU library against the FP64 oracle (task tolerance: 1 % on breakup time and
+drop velocity), on a drop that pinches off from an ink layer.  Both sides
+start from the same float32 phi and velocity fields; the oracle's series of
+row segments is reduced by the oracle's own breakup summary, the library's
+by its own (ij_get_diagnostics)."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _inputs(cfg):
+    p = cfg["params"]
+    phi_star = 0.5 * (p["rho_ink"] - p["rho_amb"])
+    phi = phi_star * np.tanh(2.0 * cfg["distance"] / p["width"])
+    phi = np.where(cfg["wall"] != 0, 0.0, phi).astype(np.float32)
+    return phi, cfg["uy"].astype(np.float32)
+
+
+def test_breakup_time_and_drop_velocity_match_oracle(oracle_mod, gpu_lib):
+    O, L = oracle_mod, gpu_lib
+    cfg = W.config_pinch_off()
+    p, wall, row0, K, steps = cfg["params"], cfg["wall"], cfg["row0"], cfg["diag_every"], cfg["steps"]
+    ny = p["ny"]
+    phi, uy = _inputs(cfg)
+
+    o = O.OracleSim(p, wall)
+    o.init_phi(phi.astype(np.float64), None, uy.astype(np.float64))
+    series = []
+    for k in range(0, steps + 1, K):
+        if o.t < k:
+            o.step(k - o.t)
+        d = o.diag(row0)
+        seg = O.segments(d["row_count"], d["row_uy"], row0, 4 * p["width"] ** 2)
+        seg["step"] = k
+        series.append(seg)
+    ref = O.breakup_summary(series, ny, p["width"])
+    o.close()
+    assert ref["breakup_step"] > 0 and np.isfinite(ref["v_drop"]), ref
+
+    g = L.Sim(dict(p, diag_row0=row0, diag_every=K), wall)
+    g.init_phi(phi, None, uy)
+    g.step(steps)
+    g.diag_sample()
+    gd = g.diagnostics()
+    print("oracle", ref, "gpu", {k: gd[k] for k in ("breakup_step", "v_drop", "vol_drop", "satellite")})
+    assert g.check() == L.IJ_OK
+    tb = ref["breakup_step"]
+    assert abs(gd["breakup_step"] - tb) <= 0.01 * tb
+    assert abs(gd["v_drop"] - ref["v_drop"]) <= 0.01 * abs(ref["v_drop"])
+    assert abs(gd["vol_drop"] - ref["vol_drop"]) <= 0.01 * ref["vol_drop"]
+    assert gd["satellite"] == ref["satellite"]

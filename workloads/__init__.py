@@ -198,6 +198,30 @@ def config_droplet_field(nx: int = 2048, ny: int = 16384, seed: int = 0,
     return cfg
 
 
+def config_pinch_off(nx: int = 96, ny: int = 320, u_blob: float = 0.05) -> dict:
+    """A drop that detaches: an ink layer on a two-row flat wall (rows 0, 1,
+    90 deg), a neck one interface width wide rising from it, and a disc of
+    radius 22 on top of the neck given an upward velocity u_blob (smoothly
+    cut off 2 nodes outside the disc).  The neck is thinner than the
+    interface profile, so it pinches and the disc detaches (breakup near
+    step 900).  Periodic in x and y; no driving force; diagnostics every 10
+    steps from row 2.  Returns the signed distance to the ink region and the
+    initial u_y."""
+    p = base_params(nx, ny, bc_y=BC_PERIODIC, force_rows=0, tau_ink=0.8)
+    wall = flat_wall(nx, ny, (0, 1))
+    cx, cy, r, neck = nx / 2.0, 120.0, 22.0, 4.0
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    x = np.arange(nx, dtype=np.float64)[None, :] + 0.5
+    d_layer = np.broadcast_to(24.0 - y, (ny, nx))
+    d_neck = np.minimum(np.minimum(neck / 2 - np.abs(x - cx), 100.0 - y), y - 10.0)
+    rb = np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
+    d = np.maximum(np.maximum(d_layer, d_neck), r - rb)
+    uy = u_blob * 0.5 * (1.0 - np.tanh((rb - r - 2.0) / 3.0))
+    uy = np.where(wall != 0, 0.0, uy)
+    return dict(name=f"pinch_off_{nx}x{ny}", params=p, wall=wall, distance=np.ascontiguousarray(d),
+                uy=np.ascontiguousarray(uy), row0=2, diag_every=10, steps=4000, nozzle=None)
+
+
 def sweep_cases(n: int = 256, seed: int = 1234, steps: int = 40000,
                 nx_range=(128, 384), ny_range=(1024, 3072), w_range=(12, 40),
                 theta_range=(30.0, 150.0), sigma_range=(0.005, 0.02),
