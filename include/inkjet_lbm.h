@@ -172,10 +172,11 @@ ij_status ij_get_moments(ij_sim *s, float *n_dev, float *phi_dev, float *ux_dev,
                          float *uy_dev, void *stream);
 
 /* Distributions of the current step into caller device arrays f [9][ny][nx]
- * and g [5][ny][nx] (solid nodes hold unspecified values). */
+ * and g [5][ny][nx]; solid nodes carry no populations and read as 0. */
 ij_status ij_get_state(ij_sim *s, float *f_dev, float *g_dev, void *stream);
 
-/* Overwrite the distributions (same layout) and the step counter. */
+/* Overwrite the distributions (same layout; entries at solid nodes are
+ * ignored) and the step counter. */
 ij_status ij_set_state(ij_sim *s, const float *f_dev, const float *g_dev, int64_t t,
                        void *stream);
 
@@ -210,6 +211,68 @@ ij_status ij_derived(const ij_sim *s, double out[8]);
  * 4 waves (256 columns) by 32 rows.  0 keeps the current value.  Results
  * do not depend on the tile shape (bit for bit). */
 ij_status ij_set_tiling(ij_sim *s, int32_t waves_x, int32_t rows_per_block);
+
+/* ------------------------------------------------------------------ batches
+ *
+ * A batch steps many independent lattices (a parameter sweep over contact
+ * angle, surface tension and pulse, with lattices of different sizes) as
+ * one: each launch of the step covers the tiles of every case, and the steps
+ * between two diagnostics samples can replay as one captured graph.  Every
+ * case is an ij_sim owned by the batch: set it up, initialise it and read it
+ * back with the single-lattice calls on the handle from ij_batch_case; it is
+ * stepped only by ij_batch_step (ij_step, ij_step_reference,
+ * ij_set_tiling and ij_attach_buffers on it return IJ_ERR_STATE, and
+ * ij_destroy on it does nothing).  The update of each case is the same, bit
+ * for bit, as stepping it alone; a case whose diagnostics sample fails the
+ * stability guard is frozen on the device and reports the step
+ * (ij_get_diagnostics on its handle) while the others go on.
+ */
+typedef struct ij_batch ij_batch;
+
+/* n cases (1..65535), each validated as by ij_create (a nozzle from its
+ * nozzle_* fields, or no wall); every case must have the same diag_every.
+ * On failure *out is NULL and ij_batch_last_error(NULL) has the reason. */
+ij_status ij_batch_create(const ij_params *cases, int32_t n, ij_batch **out);
+
+/* Frees the batch and every case handle (waits for its device work). */
+void ij_batch_destroy(ij_batch *b);
+
+const char *ij_batch_last_error(const ij_batch *b);
+
+/* Number of cases, or -1 for NULL. */
+int32_t ij_batch_size(const ij_batch *b);
+
+/* Borrowed handle of case i (valid until ij_batch_destroy). */
+ij_status ij_batch_case(ij_batch *b, int32_t i, ij_sim **out);
+
+/* Step counter shared by the cases. */
+int64_t ij_batch_time(const ij_batch *b);
+
+/* Advance every case nsteps steps (Eqs. 3-10 with each case's pulse; a
+ * diagnostics sample of every case before each step whose index is a
+ * multiple of diag_every).  Every case must be initialised and at the same
+ * step (all cases re-initialised count as step 0).  Asynchronous; it
+ * synchronises only when a case's sample store fills up. */
+ij_status ij_batch_step(ij_batch *b, int64_t nsteps, void *stream);
+
+/* Replay the steps as captured graphs of about steps_per_graph steps
+ * (rounded to a multiple of 2 and of diag_every); 0 (default) launches each
+ * kernel.  Results are the same either way. */
+ij_status ij_batch_set_graph(ij_batch *b, int32_t steps_per_graph);
+
+/* Tile shape of every case: waves across x per workgroup (1, 2 or 4) and
+ * rows per workgroup (1..1024). */
+ij_status ij_batch_set_tiling(ij_batch *b, int32_t waves_x, int32_t rows_per_block);
+ij_status ij_batch_get_tiling(const ij_batch *b, int32_t *waves_x, int32_t *rows_per_block);
+
+/* Autotuner: time trial_steps steps (2..10000) of the batch for each
+ * candidate tile shape (1, 2, 4 waves x 16, 32, 64 rows) and keep the
+ * fastest; the state of every case is restored afterwards (the step counter
+ * does not move).  Results are cached for the process by the cases' sizes
+ * and walls: a cached shape is applied without timing (*ms_per_step = -1).
+ * Outputs may be NULL.  Synchronises the stream. */
+ij_status ij_batch_autotune(ij_batch *b, int32_t trial_steps, void *stream, int32_t *waves_x,
+                            int32_t *rows_per_block, double *ms_per_step);
 
 #ifdef __cplusplus
 }

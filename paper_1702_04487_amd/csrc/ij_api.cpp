@@ -11,57 +11,16 @@
 #include <string>
 #include <vector>
 
-#include "inkjet_lbm.h"
-#include "lbm_core.h"
+#include "ij_internal.h"
 
 using ij::KParams;
+using namespace ij_host;
 
 namespace {
-
 thread_local std::string g_create_error;
-
-constexpr int kPitchAlign = 64;  // floats: 256-byte rows
-constexpr int64_t kSampleCap = 4096;
-constexpr int kGeneralRows = 4;   // rows per tile of the launch over rows next to solid nodes
-
-int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
-
-// one distribution buffer: 14 float planes and the 16-bit g_0 remainder plane
-size_t buffer_bytes(size_t plane) { return plane * (ij::kFloatPlanes * sizeof(float) + sizeof(uint16_t)); }
-
 }  // namespace
 
-struct ij_sim {
-    ij_params p{};
-    int nx = 0, ny = 0, pitch = 0;
-    size_t plane = 0;  // floats per plane
-    double phi_star = 0, n0 = 0, beta = 0, kappa = 0, q = 0, wet_in = 0, wet_out = 0;
-    KParams K{};
-    float* buf[2] = {nullptr, nullptr};
-    bool own[2] = {false, false};
-    int cur = 0;
-    uint8_t* wall = nullptr;   // device [ny][pitch]
-    std::vector<uint8_t> wall_host;  // [ny][nx]
-    double* phi = nullptr;     // device phi~ field [ny][pitch] (double)
-    int2* ghost = nullptr;     // solid nodes that touch fluid
-    int n_ghost = 0;
-    ij::DiagRow* rows = nullptr;
-    ij::SampleRec* samples = nullptr;  // device ring of kSampleCap
-    int64_t n_dev_samples = 0;         // recorded on the device, not yet drained
-    std::vector<ij_sample> host_samples;
-    int64_t t = 0;
-    bool initialised = false;
-    int64_t unstable_step = -1;
-    int waves_x = 4, rows_per_block = 32;
-    // rows of each strip the plain collide-stream path may take, and the
-    // tiles that hold the other rows (rebuilt with the wall or the tiling)
-    uint8_t* plain = nullptr;
-    int* gtiles = nullptr;
-    int n_gtiles = 0;
-    std::string err;
-};
-
-namespace {
+namespace ij_host {
 
 ij_status fail(ij_sim* s, ij_status st, const std::string& msg)
 {
@@ -275,6 +234,12 @@ ij_status build_plain(ij_sim* s)
             for (int y = y0; y < y1 && !general; ++y) general = !plain[(size_t)k * ny + y];
             if (general) tiles.push_back(b * n_strips + k);
         }
+    s->n_strips = n_strips;
+    s->n_rb = (ny + s->rows_per_block - 1) / s->rows_per_block;
+    s->gtiles_host = tiles;
+    s->n_strips = n_strips;
+    s->n_rb = (ny + s->rows_per_block - 1) / s->rows_per_block;
+    s->gtiles_host = tiles;
     if (s->plain) (void)hipFree(s->plain);
     if (s->gtiles) (void)hipFree(s->gtiles);
     s->plain = nullptr;
@@ -290,6 +255,10 @@ ij_status build_plain(ij_sim* s)
     return IJ_OK;
 }
 
+// stability guard of the diagnostics samples: non-finite nodes or max |u|
+// above this limit
+double u_limit(const ij_params& p) { return p.u_limit > 0 ? p.u_limit : 0.3; }
+
 ij_status drain_samples(ij_sim* s, hipStream_t st)
 {
     if (s->n_dev_samples == 0) return IJ_OK;
@@ -301,8 +270,7 @@ ij_status drain_samples(ij_sim* s, hipStream_t st)
         ij_sample o;
         std::memcpy(&o, &r, sizeof o);
         s->host_samples.push_back(o);
-        const double lim = s->p.u_limit > 0 ? s->p.u_limit : 0.3;
-        if (s->unstable_step < 0 && (o.nan_count > 0 || !(o.max_u <= lim))) s->unstable_step = o.step;
+        if (s->unstable_step < 0 && (o.nan_count > 0 || !(o.max_u <= u_limit(s->p)))) s->unstable_step = o.step;
     }
     s->n_dev_samples = 0;
     return IJ_OK;
@@ -325,7 +293,22 @@ ij_status record_sample(ij_sim* s, hipStream_t st)
     return IJ_OK;
 }
 
-}  // namespace
+}  // namespace ij_host
+
+void ij_host::destroy_sim(ij_sim* s)
+{
+    if (!s) return;
+    for (int b = 0; b < 2; ++b)
+        if (s->own[b] && s->buf[b]) (void)hipFree(s->buf[b]);
+    if (s->wall) (void)hipFree(s->wall);
+    if (s->phi) (void)hipFree(s->phi);
+    if (s->ghost) (void)hipFree(s->ghost);
+    if (s->rows) (void)hipFree(s->rows);
+    if (s->samples) (void)hipFree(s->samples);
+    if (s->plain) (void)hipFree(s->plain);
+    if (s->gtiles) (void)hipFree(s->gtiles);
+    delete s;
+}
 
 extern "C" {
 
@@ -414,24 +397,17 @@ ij_status ij_create(const ij_params* p, ij_sim** out)
 
 void ij_destroy(ij_sim* s)
 {
-    if (!s) return;
-    for (int b = 0; b < 2; ++b)
-        if (s->own[b] && s->buf[b]) (void)hipFree(s->buf[b]);
-    if (s->wall) (void)hipFree(s->wall);
-    if (s->phi) (void)hipFree(s->phi);
-    if (s->ghost) (void)hipFree(s->ghost);
-    if (s->rows) (void)hipFree(s->rows);
-    if (s->samples) (void)hipFree(s->samples);
-    if (s->plain) (void)hipFree(s->plain);
-    if (s->gtiles) (void)hipFree(s->gtiles);
-    delete s;
+    if (!s || s->in_batch) return;   // batch members go with their batch
+    ij_host::destroy_sim(s);
 }
+
 
 const char* ij_last_error(const ij_sim* s) { return s ? s->err.c_str() : g_create_error.c_str(); }
 
 ij_status ij_attach_buffers(ij_sim* s, void* a, void* b, size_t bytes_each)
 {
     if (!s) return IJ_ERR_INVALID_ARG;
+    if (s->in_batch) return fail(s, IJ_ERR_STATE, "a batch member keeps the buffers of its batch");
     if (!a || !b || a == b) return fail(s, IJ_ERR_INVALID_ARG, "need two distinct device buffers");
     const size_t need = buffer_bytes(s->plane);
     if (bytes_each < need) return fail(s, IJ_ERR_INVALID_ARG, "buffers smaller than ij_required_bytes");
@@ -504,6 +480,7 @@ ij_status ij_init_default(ij_sim* s, void* stream)
 ij_status ij_step(ij_sim* s, int64_t nsteps, void* stream)
 {
     if (!s) return IJ_ERR_INVALID_ARG;
+    if (s->in_batch) return fail(s, IJ_ERR_STATE, "a batch member is stepped by its batch (ij_batch_step)");
     if (!s->initialised) return fail(s, IJ_ERR_STATE, "step before init");
     if (nsteps < 0) return fail(s, IJ_ERR_INVALID_ARG, "nsteps < 0");
     if (s->unstable_step >= 0) return fail(s, IJ_ERR_UNSTABLE, "a diagnostics sample failed the stability guard");
@@ -529,6 +506,7 @@ ij_status ij_step(ij_sim* s, int64_t nsteps, void* stream)
 ij_status ij_step_reference(ij_sim* s, int64_t nsteps, void* stream)
 {
     if (!s) return IJ_ERR_INVALID_ARG;
+    if (s->in_batch) return fail(s, IJ_ERR_STATE, "a batch member is stepped by its batch (ij_batch_step)");
     if (!s->initialised) return fail(s, IJ_ERR_STATE, "step before init");
     hipStream_t st = (hipStream_t)stream;
     for (int64_t k = 0; k < nsteps; ++k) {
@@ -561,7 +539,7 @@ ij_status ij_get_state(ij_sim* s, float* f, float* g, void* stream)
 {
     if (!s) return IJ_ERR_INVALID_ARG;
     if (!s->initialised) return fail(s, IJ_ERR_STATE, "state before init");
-    hipError_t e = ij::launch_state_io(s->K, s->buf[s->cur], f, g, 1, (hipStream_t)stream);
+    hipError_t e = ij::launch_state_io(s->K, s->buf[s->cur], s->wall, f, g, 1, (hipStream_t)stream);
     return e == hipSuccess ? IJ_OK : hip_fail(s, e, "state readback kernel");
 }
 
@@ -570,7 +548,7 @@ ij_status ij_set_state(ij_sim* s, const float* f, const float* g, int64_t t, voi
     if (!s) return IJ_ERR_INVALID_ARG;
     if (!f || !g) return fail(s, IJ_ERR_INVALID_ARG, "f and g are required");
     if (t < 0) return fail(s, IJ_ERR_INVALID_ARG, "t < 0");
-    hipError_t e = ij::launch_state_io(s->K, s->buf[s->cur], (float*)f, (float*)g, 0, (hipStream_t)stream);
+    hipError_t e = ij::launch_state_io(s->K, s->buf[s->cur], s->wall, (float*)f, (float*)g, 0, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(s, e, "state write kernel");
     s->t = t;
     s->initialised = true;
@@ -679,6 +657,7 @@ ij_status ij_derived(const ij_sim* s, double out[8])
 ij_status ij_set_tiling(ij_sim* s, int32_t waves_x, int32_t rows_per_block)
 {
     if (!s) return IJ_ERR_INVALID_ARG;
+    if (s->in_batch) return fail(s, IJ_ERR_STATE, "a batch member takes the batch's tiling (ij_batch_set_tiling)");
     if (waves_x != 0 && waves_x != 1 && waves_x != 2 && waves_x != 4)
         return fail(s, IJ_ERR_INVALID_ARG, "waves_x must be 1, 2 or 4");
     if (rows_per_block < 0 || rows_per_block > 1024)

@@ -41,6 +41,22 @@ struct SampleRec {
     int64_t largest_top;
 };
 
+// One lattice of a batch as the batched kernels see it (device memory).
+struct CaseRec {
+    KParams P;              // fb unused: the pulse below gives it per step
+    float* buf[2];          // distribution buffers; buf[0] holds the state at parity 0
+    const uint8_t* wall;    // [ny][pitch]
+    const uint8_t* plain;   // plain-row table [n_strips][ny]
+    double* phi;            // phi~ field of the diagnostics [ny][pitch]
+    const int2* ghost;      // solid nodes that touch fluid
+    DiagRow* rows;          // [ny]
+    SampleRec* ring;        // diagnostics records
+    int n_ghost, n_strips, row0, a_min;
+    int64_t t_pos, t_neg, t_idle;
+    int periodic;
+    double f_pos, f_neg, u_limit;
+};
+
 hipError_t launch_phi_ghost(const KParams& P, const float* A, const uint8_t* wall, double* phi,
                             const int2* ghost_list, int n_ghost, hipStream_t st);
 hipError_t launch_collide_ref(const KParams& P, const float* A, float* B, const uint8_t* wall,
@@ -57,9 +73,24 @@ hipError_t launch_init(const KParams& P, float* A, const uint8_t* wall, double* 
                        int n_ghost, hipStream_t st);
 hipError_t launch_moments(const KParams& P, const float* A, const uint8_t* wall, const double* phi, float* n,
                           float* ph, float* ux, float* uy, hipStream_t st);
-hipError_t launch_state_io(const KParams& P, float* A, float* f_ext, float* g_ext, int to_ext,
+hipError_t launch_state_io(const KParams& P, float* A, const uint8_t* wall, float* f_ext, float* g_ext, int to_ext,
                            hipStream_t st);
 hipError_t launch_diag(const KParams& P, const float* A, const uint8_t* wall, const double* phi, int row0,
                        int a_min, int64_t step, DiagRow* rows, SampleRec* out, hipStream_t st);
+
+// Batched step work over every case.  tiles: (case, tile) pairs of the plain
+// launch (tiles of rows_per_block rows), gtiles: those of the general launch
+// (rows_general rows).  The plain launch is persistent: `grid` workgroups
+// (0 = as many as fit on the device) each run a contiguous run of tiles.
+hipError_t launch_batch_collide(const CaseRec* cases, const int2* tiles, int n_tiles, const int2* gtiles,
+                                int n_gtiles, int parity, const int64_t* t_dev, const int* active, int waves_x,
+                                int rows_per_block, int rows_general, int grid, hipStream_t st);
+hipError_t launch_batch_tick(int64_t* t_dev, hipStream_t st);
+hipError_t launch_batch_set_time(int64_t* t_dev, int64_t t, hipStream_t st);
+hipError_t launch_batch_diag(const CaseRec* cases, int n_cases, int max_nx, int max_ny, int max_ghost, int parity,
+                             const int64_t* t_dev, int64_t* n_rec, int* active, hipStream_t st);
+// workgroups of the plain batched kernel that are resident at once on the
+// current device (0 on error)
+int batch_resident_workgroups(int waves_x);
 
 } // namespace ij

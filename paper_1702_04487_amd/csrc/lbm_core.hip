@@ -21,6 +21,8 @@
 
 #include <type_traits>
 
+#include <algorithm>
+
 #include "lbm_core.h"
 
 namespace ij {
@@ -351,12 +353,9 @@ __device__ __forceinline__ void stream_shifted(const ShiftCtx& c, float v, float
 // ------------------------------------------------------ reference path kernels
 
 // raw phi at fluid nodes into the phi field (solid entries untouched)
-__global__ void k_phi_from_g(KParams P, const float* __restrict__ A, const uint8_t* __restrict__ wall,
-                             double* __restrict__ phi)
+__device__ __forceinline__ void phi_node(const KParams& P, const float* __restrict__ A,
+                                         const uint8_t* __restrict__ wall, double* __restrict__ phi, int x, int y)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
-    if (x >= P.nx) return;
     const unsigned k = (unsigned)y * P.pitch + x;
     if (wall[k]) return;
     const float* g = A + (size_t)9 * P.plane;
@@ -364,13 +363,18 @@ __global__ void k_phi_from_g(KParams P, const float* __restrict__ A, const uint8
                     g[4 * (size_t)P.plane + k], bf16_to_float(lo_plane(A, P)[k]));
 }
 
-// wetting ghosts on the list of solid nodes that touch fluid
-__global__ void k_ghost(KParams P, const int2* __restrict__ list, int n, const uint8_t* __restrict__ wall,
-                        double* __restrict__ phi)
+__global__ void k_phi_from_g(KParams P, const float* __restrict__ A, const uint8_t* __restrict__ wall,
+                             double* __restrict__ phi)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int x = list[i].x, y = list[i].y;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    if (x < P.nx) phi_node(P, A, wall, phi, x, blockIdx.y);
+}
+
+// wetting ghosts on the list of solid nodes that touch fluid
+__device__ __forceinline__ void ghost_node(const KParams& P, int2 node, const uint8_t* __restrict__ wall,
+                                           double* __restrict__ phi)
+{
+    const int x = node.x, y = node.y;
     const int dx[8] = {1, 0, -1, 0, 1, -1, -1, 1};
     const int dy[8] = {0, 1, 0, -1, 1, 1, -1, -1};
     double v[8];
@@ -388,6 +392,13 @@ __global__ void k_ghost(KParams P, const int2* __restrict__ list, int n, const u
     }
     const unsigned k0 = (unsigned)y * P.pitch + x;
     phi[k0] = ghost_value(v, m, P.wet[wall[k0]]);
+}
+
+__global__ void k_ghost(KParams P, const int2* __restrict__ list, int n, const uint8_t* __restrict__ wall,
+                        double* __restrict__ phi)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) ghost_node(P, list[i], wall, phi);
 }
 
 __device__ __forceinline__ void load_stencil(const KParams& P, const double* __restrict__ phi, int x, int y,
@@ -505,14 +516,14 @@ __device__ __forceinline__ float from_right(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x130, 0xf, 0xf, false));   // wave_shl:1
 }
 
+// One tile (strip, row block) of the fused update.  fb is the body force of
+// the step.  Shared by the single-lattice and the batched kernels; it starts
+// with a barrier so that a workgroup may run several tiles in a row.
 template <int NW, bool PLAIN>
-__global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const float* __restrict__ A,
-                                                           float* __restrict__ B,
-                                                           const uint8_t* __restrict__ wall,
-                                                           const uint8_t* __restrict__ plain_rows,
-                                                           const int* __restrict__ tile_list,
-                                                           int rows_per_block, int n_strips,
-                                                           int n_rowblocks)
+__device__ __forceinline__ void collide_tile(const KParams& P, float fb, const float* __restrict__ A,
+                                             float* __restrict__ B, const uint8_t* __restrict__ wall,
+                                             const uint8_t* __restrict__ plain_rows, int strip, int rb,
+                                             int rows_per_block)
 {
     constexpr int BW = 64 * NW;
     // raw rows rr-3..rr are in use while row rr is processed; the last
@@ -526,18 +537,7 @@ __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const floa
     __shared__ float s_out[PLAIN ? 1 : 12][BW + 2];   // post-collision f_1..f_8, h_1..h_4 of the row
     __shared__ uint8_t s_mine[kMaxRowsPerBlock];      // rows of the block this launch collides
 
-    int tile;
-    if (PLAIN) {
-        // keep runs of consecutive tiles on one XCD (workgroups are dealt
-        // round-robin over the 8 XCDs, each with its own L2)
-        const int ntiles = n_strips * n_rowblocks;
-        tile = blockIdx.x;
-        if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
-    } else {
-        tile = tile_list[blockIdx.x];
-    }
-    const int rb = tile / n_strips;
-    const int strip = tile - rb * n_strips;
+    __syncthreads();   // LDS of a previous tile of this workgroup is free
     const int x0 = strip * BW;
     const int wv = min(BW, P.nx - x0);
     const int y0 = rb * rows_per_block;
@@ -701,7 +701,7 @@ __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const floa
                 float g0h;
                 uint16_t g0l;
                 Macro mac;
-                node_collide(P, rf[S], gcur, bf16_to_float(s_lo[sc][t]), st, rc < P.force_rows ? P.fb : 0.f, fs,
+                node_collide(P, rf[S], gcur, bf16_to_float(s_lo[sc][t]), st, rc < P.force_rows ? fb : 0.f, fs,
                              h, g0h, g0l, mac);
                 const unsigned bo = boff(x, rc);
                 stf(Bf[0], bo, fs[0]);
@@ -812,6 +812,31 @@ __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const floa
     }
 }
 
+// One lattice: the PLAIN launch covers every tile, numbered row-block major
+// and dealt so that runs of consecutive tiles stay on one XCD (workgroups are
+// dealt round-robin over the 8 XCDs, each with its own L2); the other launch
+// takes the tiles of tile_list.
+template <int NW, bool PLAIN>
+__global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const float* __restrict__ A,
+                                                           float* __restrict__ B,
+                                                           const uint8_t* __restrict__ wall,
+                                                           const uint8_t* __restrict__ plain_rows,
+                                                           const int* __restrict__ tile_list,
+                                                           int rows_per_block, int n_strips,
+                                                           int n_rowblocks)
+{
+    int tile;
+    if (PLAIN) {
+        const int ntiles = n_strips * n_rowblocks;
+        tile = blockIdx.x;
+        if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+    } else {
+        tile = tile_list[blockIdx.x];
+    }
+    const int rb = tile / n_strips;
+    collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, tile - rb * n_strips, rb, rows_per_block);
+}
+
 // ------------------------------------------------------------ init / moments
 
 // raw phi of the initial state at fluid nodes: from phi itself, or
@@ -893,12 +918,19 @@ __global__ void k_moments(KParams P, const float* __restrict__ A, const uint8_t*
 
 // distributions <-> caller layout [q][ny][nx] (f without the w_i n0 shift;
 // g_0 as float(hi + lo); writing g_0 clears the remainder)
-__global__ void k_state_io(KParams P, float* __restrict__ A, float* __restrict__ ext, int to_ext, int is_f)
+// Distributions to or from unshifted [i][ny][nx] arrays.  Solid nodes carry
+// no populations: they read as 0 and are not written.
+__global__ void k_state_io(KParams P, float* __restrict__ A, const uint8_t* __restrict__ wall,
+                           float* __restrict__ ext, int to_ext, int is_f)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     const int i = blockIdx.z;
     if (x >= P.nx) return;
+    if (wall[(unsigned)y * P.pitch + x] != 0) {
+        if (to_ext) ext[(size_t)i * P.nx * P.ny + (size_t)y * P.nx + x] = 0.f;
+        return;
+    }
     const float w[9] = {4.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f,
                         1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
     const unsigned kp = (unsigned)y * P.pitch + x;
@@ -933,12 +965,10 @@ __global__ void k_state_io(KParams P, float* __restrict__ A, float* __restrict__
 // count of non-finite nodes.
 constexpr int DIAG_THREADS = 256;
 
-__global__ __launch_bounds__(DIAG_THREADS) void k_diag_rows(KParams P, const float* __restrict__ A,
-                                                           const uint8_t* __restrict__ wall,
-                                                           const double* __restrict__ phi, int row0,
-                                                           DiagRow* __restrict__ rows)
+__device__ __forceinline__ void diag_row(const KParams& P, float fb, const float* __restrict__ A,
+                                         const uint8_t* __restrict__ wall, const double* __restrict__ phi,
+                                         int row0, DiagRow* __restrict__ rows, int y)
 {
-    const int y = blockIdx.x;
     double sn = 0, sp = 0, sjx = 0, sjy = 0, suy = 0;
     float umax = 0.f;
     int cnt = 0, bad = 0;
@@ -951,7 +981,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_rows(KParams P, const flo
         for (int i = 0; i < 9; ++i) f[i] = A[(size_t)i * P.plane + k];
         load_stencil(P, phi, x, y, st);
         Macro m;
-        node_macro(P, f, st, y < P.force_rows ? P.fb : 0.f, m, Fx, Fy);
+        node_macro(P, f, st, y < P.force_rows ? fb : 0.f, m, Fx, Fy);
         sn += (double)m.n;
         sp += m.phi;
         sjx += (double)m.jx;
@@ -995,6 +1025,14 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_rows(KParams P, const flo
     }
 }
 
+__global__ __launch_bounds__(DIAG_THREADS) void k_diag_rows(KParams P, const float* __restrict__ A,
+                                                           const uint8_t* __restrict__ wall,
+                                                           const double* __restrict__ phi, int row0,
+                                                           DiagRow* __restrict__ rows)
+{
+    diag_row(P, P.fb, A, wall, phi, row0, rows, blockIdx.x);
+}
+
 // Pass 2.  Sums over rows in a fixed order.  Ink segments (maximal runs of
 // rows with ink in [row0, ny)) are found in parallel: each thread scans a
 // contiguous chunk of rows and summarises it as its first run, its last run
@@ -1010,9 +1048,10 @@ struct RunSum {
     double u;     // summed u_y
 };
 
-__global__ __launch_bounds__(DIAG_THREADS) void k_diag_finish(int ny, int row0, int a_min, int64_t step,
-                                                             const DiagRow* __restrict__ rows,
-                                                             SampleRec* __restrict__ out)
+// Thread 0 writes the record to *out and returns it (other threads return
+// an unspecified record).
+__device__ __forceinline__ SampleRec diag_finish(int ny, int row0, int a_min, int64_t step,
+                                                 const DiagRow* __restrict__ rows, SampleRec* __restrict__ out)
 {
     __shared__ double sh[4][DIAG_THREADS];
     __shared__ double smax[DIAG_THREADS];
@@ -1074,7 +1113,8 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_finish(int ny, int row0, 
         }
         __syncthreads();
     }
-    if (t != 0) return;
+    SampleRec r{};
+    if (t != 0) return r;
     long long nd = 0;
     RunSum top{-1, -1, 0, 0.0};
     auto close = [&](const RunSum& r) {
@@ -1125,7 +1165,6 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_finish(int ny, int row0, 
         }
     }
     if (has_open) close(open);
-    SampleRec r;
     r.step = step;
     r.mass_n = sh[0][0];
     r.mass_phi = sh[1][0];
@@ -1138,6 +1177,113 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_diag_finish(int ny, int row0, 
     r.largest_uy = top.u;
     r.largest_top = top.c > 0 ? top.b - 1 : -1;
     *out = r;
+    return r;
+}
+
+__global__ __launch_bounds__(DIAG_THREADS) void k_diag_finish(int ny, int row0, int a_min, int64_t step,
+                                                             const DiagRow* __restrict__ rows,
+                                                             SampleRec* __restrict__ out)
+{
+    (void)diag_finish(ny, row0, a_min, step, rows, out);
+}
+
+// ----------------------------------------------------------------- batches
+//
+// A batch holds independent lattices (cases) of different sizes and
+// parameters.  One launch per kind of step work covers every case: the
+// case records are in device memory, the current step is a device counter
+// (advanced by k_batch_tick) and the driving force of each case is evaluated
+// from it, so a captured graph of several steps replays correctly.  A case
+// whose diagnostics sample fails the stability guard is switched off on the
+// device (its state stays frozen; its samples are still recorded).
+
+// Fig. 1 pulse of a case at step t (same selection as the host's).
+__device__ __forceinline__ double case_pulse(const CaseRec& c, int64_t t)
+{
+    const int64_t period = c.t_pos + c.t_neg + c.t_idle;
+    int64_t tt = t;
+    if (c.periodic && period > 0) tt = t % period;
+    if (tt < c.t_pos) return c.f_pos;
+    if (tt < c.t_pos + c.t_neg) return -c.f_neg;
+    return 0.0;
+}
+
+// Persistent over tiles: workgroup b runs tiles [b * per_wg, (b + 1) *
+// per_wg) of the (case, tile) list, in order (neighbouring tiles of a case
+// share their halo rows through the cache).
+template <int NW, bool PLAIN>
+__global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __restrict__ cases,
+                                                           const int2* __restrict__ tiles, int n_tiles,
+                                                           int per_wg, int parity, const int64_t* __restrict__ t_dev,
+                                                           const int* __restrict__ active, int rows_per_block)
+{
+    const int64_t t = *t_dev;
+    const int i0 = blockIdx.x * per_wg, i1 = min(n_tiles, i0 + per_wg);
+    for (int i = i0; i < i1; ++i) {
+        const int2 tl = tiles[i];   // (case, tile of the case)
+        if (!active[tl.x]) continue;
+        const CaseRec& R = cases[tl.x];
+        const KParams P = R.P;
+        const float fb = (float)case_pulse(R, t);
+        const int rb = tl.y / R.n_strips;
+        collide_tile<NW, PLAIN>(P, fb, R.buf[parity], R.buf[1 - parity], R.wall, R.plain, tl.y - rb * R.n_strips,
+                                rb, rows_per_block);
+    }
+}
+
+__global__ void k_batch_tick(int64_t* t_dev)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) t_dev[0] += 1;
+}
+
+__global__ void k_batch_set_time(int64_t* t_dev, int64_t t)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) t_dev[0] = t;
+}
+
+// grid (x blocks of 256 columns, row, case)
+__global__ void k_batch_phi(const CaseRec* __restrict__ cases, int parity)
+{
+    const CaseRec& R = cases[blockIdx.z];
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x < R.P.nx && y < R.P.ny) phi_node(R.P, R.buf[parity], R.wall, R.phi, x, y);
+}
+
+// grid (blocks of 256 ghost nodes, case)
+__global__ void k_batch_ghost(const CaseRec* __restrict__ cases)
+{
+    const CaseRec& R = cases[blockIdx.y];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < R.n_ghost) ghost_node(R.P, R.ghost[i], R.wall, R.phi);
+}
+
+// grid (row, case)
+__global__ __launch_bounds__(DIAG_THREADS) void k_batch_diag_rows(const CaseRec* __restrict__ cases, int parity,
+                                                                 const int64_t* __restrict__ t_dev)
+{
+    const CaseRec& R = cases[blockIdx.y];
+    if ((int)blockIdx.x >= R.P.ny) return;
+    const KParams P = R.P;
+    diag_row(P, (float)case_pulse(R, *t_dev), R.buf[parity], R.wall, R.phi, R.row0, R.rows, blockIdx.x);
+}
+
+// grid (case): the sample goes to the case's ring at n_rec[case], which is
+// then advanced; a sample that fails the guard (non-finite nodes, or
+// max |u| above the case's limit) switches the case off.
+__global__ __launch_bounds__(DIAG_THREADS) void k_batch_diag_finish(const CaseRec* __restrict__ cases,
+                                                                   const int64_t* __restrict__ t_dev,
+                                                                   int64_t* __restrict__ n_rec,
+                                                                   int* __restrict__ active)
+{
+    const int c = blockIdx.x;
+    const CaseRec& R = cases[c];
+    const int64_t k = n_rec[c];
+    const SampleRec r = diag_finish(R.P.ny, R.row0, R.a_min, *t_dev, R.rows, R.ring + k);
+    if (threadIdx.x == 0) {
+        n_rec[c] = k + 1;
+        if (r.nan_count > 0 || !(r.max_u <= R.u_limit)) active[c] = 0;
+    }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1190,6 +1336,76 @@ hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, cons
     return hipGetLastError();
 }
 
+int batch_resident_workgroups(int waves_x)
+{
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (waves_x) {
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_collide<1, true>, 64, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_collide<2, true>, 128, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_collide<4, true>, 256, 0); break;
+    default: return 0;
+    }
+    return e == hipSuccess ? cus * per_cu : 0;
+}
+
+hipError_t launch_batch_collide(const CaseRec* cases, const int2* tiles, int n_tiles, const int2* gtiles,
+                                int n_gtiles, int parity, const int64_t* t_dev, const int* active, int waves_x,
+                                int rows_per_block, int rows_general, int grid, hipStream_t st)
+{
+    if (rows_per_block < 1 || rows_per_block > kMaxRowsPerBlock || rows_general < 1 ||
+        rows_general > kMaxRowsPerBlock || n_tiles < 0 || n_gtiles < 0 || (parity & ~1))
+        return hipErrorInvalidValue;
+    if (grid <= 0) grid = batch_resident_workgroups(waves_x);
+    if (grid <= 0) return hipErrorInvalidValue;
+    grid = n_tiles > 0 ? std::min(grid, n_tiles) : 0;
+    const int per_wg = grid > 0 ? (n_tiles + grid - 1) / grid : 0;
+    if (per_wg > 0) grid = (n_tiles + per_wg - 1) / per_wg;
+#define IJ_BLAUNCH(NWV)                                                                                       \
+    if (grid > 0)                                                                                             \
+        hipLaunchKernelGGL((k_batch_collide<NWV, true>), dim3(grid), dim3(64 * NWV), 0, st, cases, tiles,      \
+                           n_tiles, per_wg, parity, t_dev, active, rows_per_block);                          \
+    if (n_gtiles > 0)                                                                                         \
+        hipLaunchKernelGGL((k_batch_collide<NWV, false>), dim3(n_gtiles), dim3(64 * NWV), 0, st, cases, gtiles, \
+                           n_gtiles, 1, parity, t_dev, active, rows_general);
+    switch (waves_x) {
+    case 1: IJ_BLAUNCH(1) break;
+    case 2: IJ_BLAUNCH(2) break;
+    case 4: IJ_BLAUNCH(4) break;
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef IJ_BLAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tick(int64_t* t_dev, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_batch_tick, dim3(1), dim3(64), 0, st, t_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_set_time(int64_t* t_dev, int64_t t, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_batch_set_time, dim3(1), dim3(64), 0, st, t_dev, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_diag(const CaseRec* cases, int n_cases, int max_nx, int max_ny, int max_ghost, int parity,
+                             const int64_t* t_dev, int64_t* n_rec, int* active, hipStream_t st)
+{
+    if (n_cases <= 0) return hipSuccess;
+    if (n_cases > 65535 || max_ny > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_phi, dim3((max_nx + 255) / 256, max_ny, n_cases), dim3(256), 0, st, cases, parity);
+    if (max_ghost > 0)
+        hipLaunchKernelGGL(k_batch_ghost, dim3((max_ghost + 255) / 256, n_cases), dim3(256), 0, st, cases);
+    hipLaunchKernelGGL(k_batch_diag_rows, dim3(max_ny, n_cases), dim3(DIAG_THREADS), 0, st, cases, parity, t_dev);
+    hipLaunchKernelGGL(k_batch_diag_finish, dim3(n_cases), dim3(DIAG_THREADS), 0, st, cases, t_dev, n_rec, active);
+    return hipGetLastError();
+}
+
 hipError_t launch_init(const KParams& P, float* A, const uint8_t* wall, double* phi, const float* src,
                        int from_distance, const float* ux, const float* uy, const int2* ghost_list,
                        int n_ghost, hipStream_t st)
@@ -1209,13 +1425,14 @@ hipError_t launch_moments(const KParams& P, const float* A, const uint8_t* wall,
     return hipGetLastError();
 }
 
-hipError_t launch_state_io(const KParams& P, float* A, float* f_ext, float* g_ext, int to_ext, hipStream_t st)
+hipError_t launch_state_io(const KParams& P, float* A, const uint8_t* wall, float* f_ext, float* g_ext, int to_ext,
+                           hipStream_t st)
 {
     const dim3 b(256);
     if (f_ext)
-        hipLaunchKernelGGL(k_state_io, dim3((P.nx + 255) / 256, P.ny, 9), b, 0, st, P, A, f_ext, to_ext, 1);
+        hipLaunchKernelGGL(k_state_io, dim3((P.nx + 255) / 256, P.ny, 9), b, 0, st, P, A, wall, f_ext, to_ext, 1);
     if (g_ext)
-        hipLaunchKernelGGL(k_state_io, dim3((P.nx + 255) / 256, P.ny, 5), b, 0, st, P, A, g_ext, to_ext, 0);
+        hipLaunchKernelGGL(k_state_io, dim3((P.nx + 255) / 256, P.ny, 5), b, 0, st, P, A, wall, g_ext, to_ext, 0);
     return hipGetLastError();
 }
 

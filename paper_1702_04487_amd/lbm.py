@@ -57,7 +57,10 @@ EXPORTS = ["ij_params_default", "ij_create", "ij_destroy", "ij_last_error", "ij_
            "ij_attach_buffers", "ij_set_wall", "ij_init_distance", "ij_init_phi", "ij_init_default",
            "ij_step", "ij_step_reference", "ij_time", "ij_get_moments", "ij_get_state", "ij_set_state",
            "ij_diag_sample", "ij_get_row_profile", "ij_get_samples", "ij_get_diagnostics", "ij_check",
-           "ij_derived", "ij_set_tiling"]
+           "ij_derived", "ij_set_tiling",
+           "ij_batch_create", "ij_batch_destroy", "ij_batch_last_error", "ij_batch_size", "ij_batch_case",
+           "ij_batch_time", "ij_batch_step", "ij_batch_set_graph", "ij_batch_set_tiling", "ij_batch_get_tiling",
+           "ij_batch_autotune"]
 
 
 def load(path: str = LIB_PATH):
@@ -93,6 +96,18 @@ def load(path: str = LIB_PATH):
         "ij_check": (st, [vp, vp]),
         "ij_derived": (st, [vp, ctypes.POINTER(ctypes.c_double)]),
         "ij_set_tiling": (st, [vp, i32, i32]),
+        "ij_batch_create": (st, [ctypes.POINTER(IJParams), i32, ctypes.POINTER(vp)]),
+        "ij_batch_destroy": (None, [vp]),
+        "ij_batch_last_error": (ctypes.c_char_p, [vp]),
+        "ij_batch_size": (i32, [vp]),
+        "ij_batch_case": (st, [vp, i32, ctypes.POINTER(vp)]),
+        "ij_batch_time": (i64, [vp]),
+        "ij_batch_step": (st, [vp, i64, vp]),
+        "ij_batch_set_graph": (st, [vp, i32]),
+        "ij_batch_set_tiling": (st, [vp, i32, i32]),
+        "ij_batch_get_tiling": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "ij_batch_autotune": (st, [vp, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                   ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -133,16 +148,20 @@ class Sim:
     """One lattice on the GPU, owned by the library (or by caller tensors
     passed to :meth:`attach`)."""
 
-    def __init__(self, params: dict, wall: Optional[np.ndarray] = None):
+    def __init__(self, params: dict, wall: Optional[np.ndarray] = None, _handle=None):
         import torch
         self.L = load()
         self.params = dict(params)
         self.nx, self.ny = int(params["nx"]), int(params["ny"])
         self._p = to_params(params)
-        h = ctypes.c_void_p()
-        r = self.L.ij_create(ctypes.byref(self._p), ctypes.byref(h))
-        if r != IJ_OK:
-            raise LBMError(r, self.L.ij_last_error(None).decode())
+        self._owned = _handle is None
+        if _handle is None:
+            h = ctypes.c_void_p()
+            r = self.L.ij_create(ctypes.byref(self._p), ctypes.byref(h))
+            if r != IJ_OK:
+                raise LBMError(r, self.L.ij_last_error(None).decode())
+        else:
+            h = _handle
         self.h = h
         self._keep = []
         self.device = torch.device("cuda", torch.cuda.current_device())
@@ -155,7 +174,8 @@ class Sim:
 
     def close(self):
         if getattr(self, "h", None):
-            self.L.ij_destroy(self.h)
+            if self._owned:
+                self.L.ij_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -280,3 +300,72 @@ class Sim:
 
     def check(self, stream=None) -> int:
         return int(self.L.ij_check(self.h, _stream_ptr(stream)))
+
+
+class Batch:
+    """Independent lattices stepped together (:c:func:`ij_batch_create`).
+    ``cases`` is a list of parameter dicts; ``walls`` an optional list of
+    wall masks (None entries keep the nozzle of the parameters)."""
+
+    def __init__(self, cases: list, walls: Optional[list] = None):
+        self.L = load()
+        n = len(cases)
+        arr = (IJParams * n)()
+        for i, c in enumerate(cases):
+            arr[i] = to_params(c)
+        h = ctypes.c_void_p()
+        r = self.L.ij_batch_create(arr, n, ctypes.byref(h))
+        if r != IJ_OK:
+            raise LBMError(r, self.L.ij_batch_last_error(None).decode())
+        self.h = h
+        self.cases = []
+        for i, c in enumerate(cases):
+            ch = ctypes.c_void_p()
+            self._check(self.L.ij_batch_case(self.h, i, ctypes.byref(ch)))
+            w = None if walls is None else walls[i]
+            self.cases.append(Sim(c, w, _handle=ch))
+
+    def _check(self, r: int):
+        if r != IJ_OK:
+            raise LBMError(r, self.L.ij_batch_last_error(self.h).decode())
+
+    def __len__(self):
+        return len(self.cases)
+
+    def close(self):
+        if getattr(self, "h", None):
+            for c in self.cases:
+                c.h = None
+            self.L.ij_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def t(self) -> int:
+        return int(self.L.ij_batch_time(self.h))
+
+    def step(self, n: int = 1, stream=None):
+        self._check(self.L.ij_batch_step(self.h, int(n), _stream_ptr(stream)))
+
+    def set_graph(self, steps_per_graph: int):
+        self._check(self.L.ij_batch_set_graph(self.h, int(steps_per_graph)))
+
+    def set_tiling(self, waves_x: int, rows_per_block: int):
+        self._check(self.L.ij_batch_set_tiling(self.h, int(waves_x), int(rows_per_block)))
+
+    def tiling(self):
+        w, r = ctypes.c_int32(0), ctypes.c_int32(0)
+        self._check(self.L.ij_batch_get_tiling(self.h, ctypes.byref(w), ctypes.byref(r)))
+        return int(w.value), int(r.value)
+
+    def autotune(self, trial_steps: int = 20, stream=None):
+        """Returns (waves_x, rows_per_block, ms per step or -1 if cached)."""
+        w, r, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+        self._check(self.L.ij_batch_autotune(self.h, int(trial_steps), _stream_ptr(stream), ctypes.byref(w),
+                                             ctypes.byref(r), ctypes.byref(ms)))
+        return int(w.value), int(r.value), float(ms.value)

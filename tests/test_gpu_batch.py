@@ -1,0 +1,161 @@
+"""Batches of independent lattices (parameter sweeps) through the C ABI:
+every case of a batch evolves bit for bit as when it is stepped alone,
+with or without captured graphs, at any tile shape; a case that fails the
+stability guard is frozen and flagged without touching the others; the
+autotuner leaves the state unchanged."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+K = 10   # diagnostics interval of these tests
+
+
+def _cases():
+    """Four uneven cases: nozzles of different sizes, angles, tensions and
+    pulses, and a periodic box with drops and interior walls."""
+    out = []
+    for (nx, ny, x0, w, L, theta, sigma, gamma, fp, tp, fn, tn, ti, per) in [
+            (100, 72, 41, 18, 20, 60.0, 0.01, 1.0, 2e-4, 5, 1e-4, 4, 3, 1),
+            (64, 130, 24, 16, 40, 120.0, 0.005, 1.0, 1e-4, 30, 5e-5, 20, 40, 0),
+            (150, 64, 60, 24, 16, 35.0, 0.015, 0.5, 5e-5, 12, 5e-5, 12, 12, 1)]:
+        p = W.base_params(nx, ny, force_rows=L, t_pos=tp, t_neg=tn, t_idle=ti, periodic_pulse=per, f_pos=fp,
+                          f_neg=fn, tau_ink=0.8, theta_inner=theta, theta_outer=100.0, sigma=sigma, gamma=gamma,
+                          diag_every=K, diag_row0=L)
+        out.append((p, W.nozzle_wall(nx, ny, x0, w, L), W.meniscus_distance(nx, ny, L) + 2.0))
+    nx, ny = 70, 45
+    p = W.base_params(nx, ny, bc_y=W.BC_PERIODIC, theta_inner=40.0, theta_outer=135.0, tau_ink=0.75,
+                      force_rows=ny, f_pos=1e-5, t_pos=10 ** 6, diag_every=K, diag_row0=2)
+    wall = W.flat_wall(nx, ny, (0, 1))
+    wall[20:26, 30:41] = W.WALL_OUTER
+    out.append((p, wall, W.discs_distance(nx, ny, [(35.0, 12.0, 9.0), (10.0, 36.0, 6.0)])))
+    return out
+
+
+def _batch(L, cases):
+    b = L.Batch([c[0] for c in cases], [c[1] for c in cases])
+    for sim, (_, _, d) in zip(b.cases, cases):
+        sim.init_distance(d)
+    return b
+
+
+def _singles(L, cases, steps):
+    out = []
+    for p, wall, d in cases:
+        s = L.Sim(p, wall)
+        s.init_distance(d)
+        s.step(steps)
+        out.append(s)
+    return out
+
+
+def _bits(t):
+    import torch
+    return t.contiguous().view(torch.int32)
+
+
+def _same(a, b):
+    """Bit patterns of both states are equal (solid nodes read as 0)."""
+    fa, ga = a.state()
+    fb, gb = b.state()
+    return bool((_bits(fa) == _bits(fb)).all() and (_bits(ga) == _bits(gb)).all())
+
+
+def _same_samples(a, b):
+    sa, sb = a.samples(), b.samples()
+    return len(sa) == len(sb) and all(repr(x) == repr(y) for x, y in zip(sa, sb))
+
+
+def test_batch_matches_single_runs_bitwise(gpu_lib):
+    L = gpu_lib
+    cases = _cases()
+    b = _batch(L, cases)
+    b.step(57)
+    b.step(73)
+    assert b.t == 130
+    singles = _singles(L, cases, 130)
+    for i, (bc, sc) in enumerate(zip(b.cases, singles)):
+        assert bc.check() == L.IJ_OK and sc.check() == L.IJ_OK, i
+        assert bc.t == 130 and _same(bc, sc), i
+        assert _same_samples(bc, sc), i
+    with pytest.raises(L.LBMError):
+        b.cases[0].step(1)   # a member is stepped by its batch only
+    b.close()
+
+
+def test_batch_graph_replay_equals_launches(gpu_lib):
+    L = gpu_lib
+    cases = _cases()
+    ref = _batch(L, cases)
+    ref.step(3)
+    ref.step(97)
+    ref.step(45)
+    g = _batch(L, cases)
+    g.set_graph(20)
+    g.step(3)       # unaligned start, then replays of 20-step graphs and a tail
+    g.step(97)
+    g.step(45)
+    for i, (a, c) in enumerate(zip(ref.cases, g.cases)):
+        assert a.check() == L.IJ_OK, i
+        assert _same(a, c), i
+        assert _same_samples(a, c), i
+    ref.close()
+    g.close()
+
+
+def test_batch_unstable_case_is_frozen_and_flagged(gpu_lib):
+    L = gpu_lib
+    cases = _cases()
+    p, wall, d = cases[1]
+    cases[1] = (dict(p, f_pos=0.05, t_pos=10 ** 6, t_neg=0, t_idle=0, periodic_pulse=0), wall, d)
+    b = _batch(L, cases)
+    b.set_graph(20)
+    b.step(200)
+    diag = b.cases[1].diagnostics()
+    assert diag["unstable_step"] >= 0 and b.cases[1].check() == L.IJ_ERR_UNSTABLE
+    singles = _singles(L, [c for i, c in enumerate(cases) if i != 1], 200)
+    for bc, sc in zip([c for i, c in enumerate(b.cases) if i != 1], singles):
+        assert _same(bc, sc) and _same_samples(bc, sc)
+        assert bc.check() == L.IJ_OK
+    b.close()
+
+
+def test_batch_autotune_keeps_state_and_caches(gpu_lib):
+    L = gpu_lib
+    cases = _cases()
+    b = _batch(L, cases)
+    b.step(20)
+    before = [c.state() for c in b.cases]
+    w, r, ms = b.autotune(6)
+    assert (w, r) == b.tiling() and w in (1, 2, 4) and r in (16, 32, 64) and ms > 0
+    for c, (f0, g0) in zip(b.cases, before):
+        f1, g1 = c.state()
+        assert bool((f0 == f1).all() and (g0 == g1).all())
+    assert b.t == 20
+    b.step(40)
+    singles = _singles(L, cases, 60)
+    for bc, sc in zip(b.cases, singles):
+        assert _same(bc, sc) and _same_samples(bc, sc)
+    b2 = _batch(L, cases)
+    w2, r2, ms2 = b2.autotune(6)
+    assert (w2, r2) == (w, r) and ms2 == -1.0   # same shapes: from the cache
+    b.close()
+    b2.close()
+
+
+def test_batch_tile_shapes_are_bitwise_equal(gpu_lib):
+    L = gpu_lib
+    cases = _cases()
+    runs = []
+    for shape in [(1, 16), (2, 7), (4, 64)]:
+        b = _batch(L, cases)
+        b.set_tiling(*shape)
+        b.set_graph(10)
+        b.step(50)
+        runs.append(b)
+    for i in range(len(cases)):
+        assert _same(runs[0].cases[i], runs[1].cases[i]) and _same(runs[0].cases[i], runs[2].cases[i]), i
+    for b in runs:
+        b.close()
