@@ -24,6 +24,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -78,12 +80,77 @@ def cpu_baseline(cfg, rows: int = 4096, steps: int = 20) -> dict:
                       f"{steps} steps after 1 warm-up, FP64"}
 
 
+def log(msg: str) -> None:
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
+def sweep_bench(batched_steps: int = 600, plain_steps: int = 300, plain_every: int = 16) -> dict:
+    """Cases per hour of the 256-case sweep table (seed 1234, the stable
+    variant), 40000 steps per case, diagnostics every 50 steps: every case in
+    one batch (autotuned tile shape, graphs of 50 steps) timed over
+    `batched_steps` steps, against the same cases run one at a time through
+    ij_step (every `plain_every`-th case timed over `plain_steps` steps)."""
+    import torch
+    import workloads as W
+    from paper_1702_04487_amd import lbm
+    cases = W.sweep_cases(256, seed=1234, stable=True)
+    steps_case = cases[0]["steps"]
+    nodes = sum(c["params"]["nx"] * c["params"]["ny"] for c in cases)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    log(f"sweep: batch of {len(cases)} cases, {nodes / 1e6:.1f} M nodes")
+    b = lbm.Batch([c["params"] for c in cases])
+    for sim in b.cases:
+        sim.init_default()
+    w, r, tune_ms = b.autotune(10)
+    log(f"sweep: autotuned tile {w} waves x {r} rows ({tune_ms:.3f} ms per step)")
+    b.set_graph(50)
+    b.step(100)
+    ms_b = timed(lambda: b.step(batched_steps)) / batched_steps
+    unstable = sum(1 for c in b.cases if c.check() != lbm.IJ_OK)
+    b.close()
+    del b
+    log(f"sweep: batched {ms_b:.3f} ms per step, {unstable} cases flagged unstable")
+
+    per_case = []
+    for c in cases[::plain_every]:
+        sim = lbm.Sim(c["params"])
+        sim.init_default()
+        sim.step(50)
+        per_case.append(timed(lambda: sim.step(plain_steps)) / plain_steps)
+        sim.close()
+    ms_p = float(np.mean(per_case))
+    log(f"sweep: plain {ms_p:.4f} ms per case-step over {len(per_case)} sampled cases")
+    batched_cph = len(cases) * 3600.0 / (ms_b * 1e-3 * steps_case)
+    plain_cph = 3600.0 / (ms_p * 1e-3 * steps_case)
+    return {"table": "256 nozzle cases, seed 1234, stable variant (Gamma*sigma <= 0.01, pulse scaled to a "
+                     "0.2 viscous speed bound), 40000 steps each, diagnostics every 50",
+            "nodes": nodes, "steps_per_case": steps_case,
+            "plain_cases_per_hour": round(plain_cph, 1),
+            "batched_cases_per_hour": round(batched_cph, 1),
+            "batched_over_plain": round(batched_cph / plain_cph, 2),
+            "batched_ms_per_step": round(ms_b, 4), "batched_mlups": round(nodes / (ms_b * 1e-3) / 1e6, 1),
+            "plain_ms_per_case_step": round(ms_p, 5),
+            "tile": [w, r], "graph_steps": 50, "unstable_cases": unstable,
+            "timed": {"batched_steps": batched_steps, "plain_cases": len(per_case), "plain_steps": plain_steps}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the sweep cases/hour measurement")
     ap.add_argument("--kernel-steps", type=int, default=500,
                     help="launches timed back-to-back for the fused kernel's mean duration")
     ap.add_argument("--tiling", default="",
@@ -118,6 +185,7 @@ def main() -> int:
             sim.step(k)
             done += k
 
+    log(f"droplet field {nx}x{ny}: {args.warmup} warm-up steps, then {args.steps} timed")
     run(args.warmup)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -172,7 +240,12 @@ def main() -> int:
                      "copy_ceiling_gbs": COPY_CEILING_GBS},
         "mass_drift": mass_drift,
     }
+    sim.close()
+    del sim
+    if not args.no_sweep:
+        out["sweep"] = sweep_bench()
     if not args.no_cpu_baseline:
+        log("cpu baseline: the FP64 oracle on a band of the droplet field")
         out["cpu_baseline"] = cpu_baseline(cfg)
     print(json.dumps(out))
     return 0

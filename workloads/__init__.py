@@ -225,9 +225,18 @@ def config_pinch_off(nx: int = 96, ny: int = 320, u_blob: float = 0.05) -> dict:
 def sweep_cases(n: int = 256, seed: int = 1234, steps: int = 40000,
                 nx_range=(128, 384), ny_range=(1024, 3072), w_range=(12, 40),
                 theta_range=(30.0, 150.0), sigma_range=(0.005, 0.02),
-                f_range=(5e-5, 3e-4), t_range=(500, 3000), periodic_pulse=0) -> List[dict]:
+                f_range=(5e-5, 3e-4), t_range=(500, 3000), periodic_pulse=0,
+                stable: bool = False, u_cap: float = 0.2, gamma_sigma_max: float = 0.01,
+                diag_every: int = 50) -> List[dict]:
     """Seeded table of independent nozzle cases for a parameter sweep
-    (contact angle x surface tension x pulse, uneven lattice sizes)."""
+    (contact angle x surface tension x pulse, uneven lattice sizes).
+
+    With ``stable`` the table is the scaled variant used for measurement and
+    training data: the mobility Gamma is lowered so that Gamma * sigma <=
+    gamma_sigma_max (larger products are numerically unstable at W = 4), and
+    both pulse amplitudes are scaled by one factor so that the viscous
+    centreline speed of the nozzle channel, F w^2 / (8 n0 nu_ink), stays at or
+    below u_cap.  The draws (and so every other parameter) are the same."""
     rng = SplitMix64(seed)
     out = []
     for k in range(n):
@@ -243,9 +252,18 @@ def sweep_cases(n: int = 256, seed: int = 1234, steps: int = 40000,
         ti = rng.randint(*t_range)
         L = ny // 8
         x0 = (nx - w) // 2
+        gamma = 1.0
+        if stable:
+            gamma = min(1.0, gamma_sigma_max / sigma)
+            n0 = 0.5 * (1.0 + 0.1)
+            nu_ink = (0.8 - 0.5) / 3.0
+            bound = max(fp, fn) * w * w / (8.0 * n0 * nu_ink)
+            scale = min(1.0, u_cap / bound)
+            fp, fn = fp * scale, fn * scale
         p = base_params(nx, ny, force_rows=L, t_pos=tp, t_neg=tn, t_idle=ti,
                         periodic_pulse=periodic_pulse, f_pos=fp, f_neg=fn, tau_ink=0.8,
-                        theta_inner=theta, sigma=sigma)
+                        theta_inner=theta, sigma=sigma, gamma=gamma, nozzle_x0=x0, nozzle_w=w,
+                        nozzle_len=L, diag_row0=L, diag_every=diag_every)
         out.append(dict(name=f"case{k}", params=p, nozzle=(x0, w, L), row0=L, steps=steps))
     return out
 
