@@ -277,3 +277,41 @@ def case_wall(case: dict) -> np.ndarray:
 def case_distance(case: dict) -> np.ndarray:
     p = case["params"]
     return meniscus_distance(p["nx"], p["ny"], case["nozzle"][2])
+
+
+# ------------------------------------------------------------ surrogate
+def splitmix64_array(seed: int, n: int, offset: int = 0) -> np.ndarray:
+    """Outputs offset .. offset+n-1 of SplitMix64 started at `seed`
+    (vectorised; the same sequence as SplitMix64(seed).next_u64())."""
+    with np.errstate(over="ignore"):
+        k = np.arange(offset + 1, offset + n + 1, dtype=np.uint64)
+        z = np.uint64(seed & MASK64) + k * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def uniform_array(seed: int, n: int, lo: float = 0.0, hi: float = 1.0, offset: int = 0) -> np.ndarray:
+    u = (splitmix64_array(seed, n, offset) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+    return lo + (hi - lo) * u
+
+
+MLP_SIZES = (7, 128, 128, 4)
+
+
+def mlp_init(seed: int) -> dict:
+    """Initial weights of one ensemble member: W uniform in +/- 1/sqrt(fan_in),
+    biases zero (float64; W1 [128, 7], W2 [128, 128], W3 [4, 128])."""
+    out, off = {}, 0
+    for l, (fi, fo) in enumerate(zip(MLP_SIZES[:-1], MLP_SIZES[1:]), start=1):
+        a = 1.0 / math.sqrt(fi)
+        out[f"W{l}"] = uniform_array(seed, fo * fi, -a, a, off).reshape(fo, fi)
+        off += fo * fi
+        out[f"b{l}"] = np.zeros(fo)
+    return out
+
+
+def minibatch_order(seed: int, n: int, steps: int, batch: int) -> np.ndarray:
+    """[steps, batch] sample indices drawn uniformly from [0, n) (int32)."""
+    u = uniform_array(seed, steps * batch)
+    return np.minimum((u * n).astype(np.int64), n - 1).astype(np.int32).reshape(steps, batch)
