@@ -274,6 +274,67 @@ ij_status ij_batch_get_tiling(const ij_batch *b, int32_t *waves_x, int32_t *rows
 ij_status ij_batch_autotune(ij_batch *b, int32_t trial_steps, void *stream, int32_t *waves_x,
                             int32_t *rows_per_block, double *ms_per_step);
 
+/* --------------------------------------------------------------- surrogate
+ *
+ * An ensemble of small networks that predict the droplet outputs of a case
+ * (Results: breakup time and drop velocity, Figs. 4-7; drop volume and the
+ * satellite flag) from its seven inputs, so that a sweep can skip the
+ * lattice run where the members agree.  Each member is a multilayer
+ * perceptron 7 -> 128 -> 128 -> 4 with GELU (z Phi(z)), trained with Adam on
+ * float32 master weights; every product runs on the matrix cores in bfloat16
+ * with float32 accumulation.
+ *
+ * Inputs x (float32 [n][7]): contact angle (deg), surface tension sigma, f_pos,
+ * f_neg, t_pos, t_neg, t_idle; the network sees (x - x_mean) / x_std.
+ * Targets y (float32 [n][4]): breakup step, drop velocity, drop volume (the
+ * first three learned as (y - y_mean) / y_std with a squared-error loss) and
+ * the satellite flag in {0, 1} (logistic loss on the fourth output).
+ * Loss per minibatch of S rows: mean over rows of (1/3) sum of the three
+ * squared errors plus the logistic loss.
+ * Packed parameters of one member (float64, ij_mlp_param_count() = 18052
+ * values): W1 [128][7], b1 [128], W2 [128][128], b2 [128], W3 [4][128], b3 [4].
+ */
+typedef struct ij_mlp ij_mlp;
+
+/* n_members (1..64) members with zero parameters and unit scaling. */
+ij_status ij_mlp_create(int32_t n_members, ij_mlp **out);
+void ij_mlp_destroy(ij_mlp *m);
+const char *ij_mlp_last_error(const ij_mlp *m);
+int32_t ij_mlp_param_count(void);
+
+/* Parameters of one member from / to a host array in the packed layout;
+ * setting them resets that member's Adam moments and the step count.
+ * Synchronise the device. */
+ij_status ij_mlp_set_weights(ij_mlp *m, int32_t member, const double *packed);
+ij_status ij_mlp_get_weights(ij_mlp *m, int32_t member, double *packed);
+
+/* Input and target scaling (host arrays of 7, 7, 3, 3; std > 0). */
+ij_status ij_mlp_set_scaling(ij_mlp *m, const double *x_mean, const double *x_std, const double *y_mean,
+                             const double *y_std);
+
+/* Loss and its gradient with respect to every parameter, for every member,
+ * over rows 0..n-1 (1..1024) of the device arrays x, y: grad (host,
+ * [n_members][18052] packed), loss (host, [n_members], may be NULL).
+ * Synchronises the stream. */
+ij_status ij_mlp_gradients(ij_mlp *m, const float *x_dev, const float *y_dev, int32_t n, double *grad,
+                           double *loss, void *stream);
+
+/* `steps` Adam steps (b1 0.9, b2 0.999, eps 1e-8, learning rate lr) of every
+ * member; member k's step s uses rows idx[k][s][0..batch) (device int32,
+ * [n_members][steps][batch], clamped to [0, n_rows)) of x, y; batch
+ * 1..1024.  loss (device [n_members][steps], may be NULL) gets each step's
+ * minibatch loss before its update.  Asynchronous. */
+ij_status ij_mlp_train(ij_mlp *m, const float *x_dev, const float *y_dev, int32_t n_rows, const int32_t *idx_dev,
+                       int32_t steps, int32_t batch, float lr, float *loss_dev, void *stream);
+
+/* Ensemble prediction for n queries (device x [n][7]): mean and spread
+ * (standard deviation over the members) of each output (device [n][4]:
+ * breakup step, drop velocity, drop volume in target units, and the
+ * satellite probability); members (device [n_members][n][4]) optional.
+ * Asynchronous. */
+ij_status ij_mlp_predict(ij_mlp *m, const float *x_dev, int64_t n, float *mean_dev, float *spread_dev,
+                         float *members_dev, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,7 +60,9 @@ EXPORTS = ["ij_params_default", "ij_create", "ij_destroy", "ij_last_error", "ij_
            "ij_derived", "ij_set_tiling",
            "ij_batch_create", "ij_batch_destroy", "ij_batch_last_error", "ij_batch_size", "ij_batch_case",
            "ij_batch_time", "ij_batch_step", "ij_batch_set_graph", "ij_batch_set_tiling", "ij_batch_get_tiling",
-           "ij_batch_autotune"]
+           "ij_batch_autotune",
+           "ij_mlp_create", "ij_mlp_destroy", "ij_mlp_last_error", "ij_mlp_param_count", "ij_mlp_set_weights",
+           "ij_mlp_get_weights", "ij_mlp_set_scaling", "ij_mlp_gradients", "ij_mlp_train", "ij_mlp_predict"]
 
 
 def load(path: str = LIB_PATH):
@@ -108,6 +110,16 @@ def load(path: str = LIB_PATH):
         "ij_batch_get_tiling": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "ij_batch_autotune": (st, [vp, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                    ctypes.POINTER(ctypes.c_double)]),
+        "ij_mlp_create": (st, [i32, ctypes.POINTER(vp)]),
+        "ij_mlp_destroy": (None, [vp]),
+        "ij_mlp_last_error": (ctypes.c_char_p, [vp]),
+        "ij_mlp_param_count": (i32, []),
+        "ij_mlp_set_weights": (st, [vp, i32, vp]),
+        "ij_mlp_get_weights": (st, [vp, i32, vp]),
+        "ij_mlp_set_scaling": (st, [vp, vp, vp, vp, vp]),
+        "ij_mlp_gradients": (st, [vp, vp, vp, i32, vp, vp, vp]),
+        "ij_mlp_train": (st, [vp, vp, vp, i32, vp, i32, i32, ctypes.c_float, vp, vp]),
+        "ij_mlp_predict": (st, [vp, vp, i64, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -369,3 +381,114 @@ class Batch:
         self._check(self.L.ij_batch_autotune(self.h, int(trial_steps), _stream_ptr(stream), ctypes.byref(w),
                                              ctypes.byref(r), ctypes.byref(ms)))
         return int(w.value), int(r.value), float(ms.value)
+
+
+MLP_NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")
+MLP_SHAPES = {"W1": (128, 7), "b1": (128,), "W2": (128, 128), "b2": (128,), "W3": (4, 128), "b3": (4,)}
+
+
+def pack_params(p: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(p[k], np.float64).reshape(-1) for k in MLP_NAMES])
+
+
+def unpack_params(v: np.ndarray) -> dict:
+    out, off = {}, 0
+    for k in MLP_NAMES:
+        n = int(np.prod(MLP_SHAPES[k]))
+        out[k] = v[off:off + n].reshape(MLP_SHAPES[k]).copy()
+        off += n
+    return out
+
+
+class MLP:
+    """Ensemble of surrogate networks (:c:func:`ij_mlp_create`)."""
+
+    def __init__(self, n_members: int = 4):
+        import torch
+        self.L = load()
+        h = ctypes.c_void_p()
+        r = self.L.ij_mlp_create(int(n_members), ctypes.byref(h))
+        if r != IJ_OK:
+            raise LBMError(r, self.L.ij_mlp_last_error(None).decode())
+        self.h = h
+        self.n_members = int(n_members)
+        self.n_params = int(self.L.ij_mlp_param_count())
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def _check(self, r: int):
+        if r != IJ_OK:
+            raise LBMError(r, self.L.ij_mlp_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.ij_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _f32(self, a, cols):
+        import torch
+        t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=self.device) \
+            if not isinstance(a, torch.Tensor) else a.to(self.device, torch.float32).contiguous()
+        if t.dim() != 2 or t.shape[1] != cols:
+            raise ValueError(f"expected an [n, {cols}] array, got {tuple(t.shape)}")
+        return t
+
+    def set_weights(self, member: int, params: dict):
+        v = np.ascontiguousarray(pack_params(params))
+        assert v.size == self.n_params
+        self._check(self.L.ij_mlp_set_weights(self.h, int(member), v.ctypes.data_as(ctypes.c_void_p)))
+
+    def get_weights(self, member: int) -> dict:
+        v = np.zeros(self.n_params)
+        self._check(self.L.ij_mlp_get_weights(self.h, int(member), v.ctypes.data_as(ctypes.c_void_p)))
+        return unpack_params(v)
+
+    def set_scaling(self, x_mean, x_std, y_mean, y_std):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x_mean, x_std, y_mean, y_std)]
+        assert [a.size for a in arrs] == [7, 7, 3, 3]
+        self._keep_scaling = arrs
+        self._check(self.L.ij_mlp_set_scaling(self.h, *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs]))
+
+    def gradients(self, x, y, stream=None):
+        """(loss [members], list of packed-gradient dicts per member)."""
+        xt, yt = self._f32(x, 7), self._f32(y, 4)
+        g = np.zeros((self.n_members, self.n_params))
+        l = np.zeros(self.n_members)
+        self._check(self.L.ij_mlp_gradients(self.h, _dptr(xt), _dptr(yt), int(xt.shape[0]),
+                                            g.ctypes.data_as(ctypes.c_void_p), l.ctypes.data_as(ctypes.c_void_p),
+                                            _stream_ptr(stream)))
+        return l, [unpack_params(g[k]) for k in range(self.n_members)]
+
+    def train(self, x, y, idx, lr: float, stream=None):
+        """idx: int array [n_members, steps, batch]; returns the per-step
+        losses [n_members, steps] (a device tensor)."""
+        import torch
+        xt, yt = self._f32(x, 7), self._f32(y, 4)
+        it = torch.as_tensor(np.ascontiguousarray(idx, dtype=np.int32), device=self.device)
+        if it.dim() != 3 or it.shape[0] != self.n_members:
+            raise ValueError("idx must be [n_members, steps, batch]")
+        loss = torch.zeros((self.n_members, it.shape[1]), device=self.device, dtype=torch.float32)
+        self._check(self.L.ij_mlp_train(self.h, _dptr(xt), _dptr(yt), int(xt.shape[0]),
+                                        ctypes.c_void_p(it.data_ptr()), int(it.shape[1]), int(it.shape[2]),
+                                        float(lr), _dptr(loss), _stream_ptr(stream)))
+        self._keep_train = (xt, yt, it)
+        return loss
+
+    def predict(self, x, members: bool = False, stream=None):
+        """(mean [n, 4], spread [n, 4]) device tensors, and the per-member
+        outputs [n_members, n, 4] when members is set."""
+        import torch
+        xt = self._f32(x, 7)
+        n = int(xt.shape[0])
+        mean = torch.empty((n, 4), device=self.device, dtype=torch.float32)
+        spread = torch.empty((n, 4), device=self.device, dtype=torch.float32)
+        mem = torch.empty((self.n_members, n, 4), device=self.device, dtype=torch.float32) if members else None
+        self._check(self.L.ij_mlp_predict(self.h, _dptr(xt), n, _dptr(mean), _dptr(spread),
+                                          _dptr(mem) if mem is not None else None, _stream_ptr(stream)))
+        self._keep_pred = xt
+        return (mean, spread, mem) if members else (mean, spread)
