@@ -144,6 +144,54 @@ def sweep_bench(batched_steps: int = 600, plain_steps: int = 300, plain_every: i
             "timed": {"batched_steps": batched_steps, "plain_cases": len(per_case), "plain_steps": plain_steps}}
 
 
+def surrogate_bench(queries: int = 100000, held: int = 256) -> dict:
+    """The sweep surrogate on the stored solver cases: train the 4-member
+    ensemble (the library's kernels), calibrate its trust threshold on a 10 %
+    split, judge it on `held` held-out cases, then answer `queries` new
+    query points with the network where it is trusted and the solver
+    elsewhere.  Solver cost per case: a timed batched run."""
+    import torch
+    from paper_1702_04487_amd import surrogate as S
+    x, y, horizon, _ = S.load_dataset()
+    xt, yt, xh, yh = x[:-held], y[:-held], x[-held:], y[-held:]
+    ncal = len(xt) // 10
+    sur = S.Surrogate(4)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sur.fit(xt[:-ncal], yt[:-ncal], steps=3000)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    pc, sc = sur.predict(xt[-ncal:])
+    thr = S.calibrate(sc, *S.errors(pc, yt[-ncal:]))
+    ph, sh = sur.predict(xh)
+    ans = sh <= thr
+    et, ev = S.errors(ph, yh)
+    xq = S.sample_inputs(queries, 4242)
+    sur.predict(xq)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, sq = sur.predict(xq)
+    torch.cuda.synchronize()
+    t_pred = time.perf_counter() - t0
+    aq = float(np.mean(sq <= thr))
+    log(f"surrogate: trained in {t_train:.2f} s; answers {aq:.3f} of {queries} queries in {t_pred * 1e3:.2f} ms")
+    t_case = S.solver_seconds_per_case(xh, horizon)
+    solver_cph = 3600.0 / t_case
+    with_cph = queries * 3600.0 / (t_pred + (1.0 - aq) * queries * t_case)
+    return {"cases": "256 x 2048 nozzle (w 32, L 256), 7 sweep inputs, periodic pulse, stable variant, "
+                     f"{horizon} steps; {len(x)} stored solver cases ({len(xt) - ncal} train, {ncal} calibrate, "
+                     f"{held} held out)",
+            "members": 4, "train_seconds": round(t_train, 3), "threshold": thr,
+            "held_out": {"answered": int(ans.sum()), "of": held,
+                         "mean_err_breakup": float(et[ans].mean()) if ans.any() else None,
+                         "mean_err_v_drop": float(ev[ans].mean()) if ans.any() else None},
+            "queries": queries, "answered_fraction": round(aq, 4), "predict_ms": round(t_pred * 1e3, 3),
+            "solver_seconds_per_case": round(t_case, 4),
+            "batched_cases_per_hour": round(solver_cph, 1),
+            "batched_surrogate_cases_per_hour": round(with_cph, 1),
+            "gain": round(with_cph / solver_cph, 3)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +292,7 @@ def main() -> int:
     del sim
     if not args.no_sweep:
         out["sweep"] = sweep_bench()
+        out["sweep"]["surrogate"] = surrogate_bench()
     if not args.no_cpu_baseline:
         log("cpu baseline: the FP64 oracle on a band of the droplet field")
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -193,20 +193,27 @@ ij_status upload_wall(ij_sim* s)
 }
 
 // Plain rows: for strip k (columns [x0, x0 + w) with two halo columns each
-// side) row r is plain when rows r-1..r+1 hold no solid node in those
-// columns and, with open rows, 1 <= r <= ny-2.  Tiles (strip, block of rows)
-// that contain any other row go to the general launch.
+// side; strips are 64 * waves_x columns wide, and with mixed strips the
+// columns past the last full one go to 64-column strips) row r is plain
+// when rows r-1..r+1 hold no solid node in those columns and, with open
+// rows, 1 <= r <= ny-2.  Tiles (strip, block of rows) that contain any
+// other row go to the general launch.
 ij_status build_plain(ij_sim* s)
 {
     const int nx = s->nx, ny = s->ny;
     const int bw = 64 * s->waves_x;
-    const int n_strips = (nx + bw - 1) / bw;
+    // strips of bw columns; with mixed strips the columns past the last full
+    // one go to strips of 64 (one wave) instead of a partly idle wide strip
+    const int n_wide = s->mixed_strips ? nx / bw : (nx + bw - 1) / bw;
+    const int n_strips = n_wide + (s->mixed_strips ? (nx - n_wide * bw + 63) / 64 : 0);
+    auto strip_x0 = [&](int k) { return k < n_wide ? k * bw : n_wide * bw + (k - n_wide) * 64; };
+    auto strip_w = [&](int k) { return std::min(k < n_wide ? bw : 64, nx - strip_x0(k)); };
     const bool open = s->p.bc_y == IJ_BC_OPEN;
     // rows with any solid node in a column window: per strip
     std::vector<uint8_t> plain((size_t)n_strips * ny, 0);
     std::vector<int> tiles;
     for (int k = 0; k < n_strips; ++k) {
-        const int x0 = k * bw, w = std::min(bw, nx - x0);
+        const int x0 = strip_x0(k), w = strip_w(k);
         std::vector<uint8_t> solid_row(ny, 0);
         for (int y = 0; y < ny; ++y)
             for (int c = x0 - 2; c < x0 + w + 2 && !solid_row[y]; ++c)
@@ -235,9 +242,11 @@ ij_status build_plain(ij_sim* s)
             if (general) tiles.push_back(b * n_strips + k);
         }
     s->n_strips = n_strips;
+    s->n_wide = n_wide;
     s->n_rb = (ny + s->rows_per_block - 1) / s->rows_per_block;
     s->gtiles_host = tiles;
     s->n_strips = n_strips;
+    s->n_wide = n_wide;
     s->n_rb = (ny + s->rows_per_block - 1) / s->rows_per_block;
     s->gtiles_host = tiles;
     if (s->plain) (void)hipFree(s->plain);

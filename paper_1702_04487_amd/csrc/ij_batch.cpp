@@ -36,12 +36,13 @@ struct ij_batch {
     int64_t t = 0;
     int64_t diag_every = 0;
     int graph_steps = 0;   // steps per captured graph, 0: plain launches
-    // device tables
+    // device tables: (case, strip, row block) tiles of the wide and the
+    // 64-column tail strips, plain and general, in one allocation
     ij::CaseRec* d_cases = nullptr;
-    int2* d_tiles = nullptr;
-    int2* d_gtiles = nullptr;
-    int n_tiles = 0, n_gtiles = 0, cap_tiles = 0, cap_gtiles = 0;
-    std::vector<int2> tiles_host, gtiles_host;
+    int4* d_tiles = nullptr;
+    size_t cap_tiles = 0;
+    std::vector<int4> tiles_host;   // wide | tail | general wide | general tail
+    ij::BatchTiles T{};
     int64_t* d_t = nullptr;
     int64_t* d_nrec = nullptr;
     int* d_active = nullptr;
@@ -51,14 +52,12 @@ struct ij_batch {
     int* h_active = nullptr;
     hipEvent_t staged = nullptr;   // the uploads of the last call have been read
     int max_nx = 0, max_ny = 0, max_ghost = 0;
-    int grid = 0;                  // persistent workgroups of the plain launch
     // graph of graph_steps steps starting at a step that is a multiple of it
     hipStream_t cs = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_len = 0;
-    std::vector<int2> graph_tiles, graph_gtiles;
     std::string err;
 };
 
@@ -113,15 +112,18 @@ int64_t graph_period(const ij_batch* b)
     return (want + unit - 1) / unit * unit;
 }
 
-// (case, tile) lists of both launches from the members' current tilings
+// tile lists of the launches from the members' current tilings
 ij_status build_tiles(ij_batch* b)
 {
-    std::vector<int2> tl, gl;
+    std::vector<int4> lists[4];   // wide, tail, general wide, general tail
     for (size_t c = 0; c < b->sims.size(); ++c) {
         const ij_sim* s = b->sims[c];
-        const int n = s->n_strips * s->n_rb;
-        for (int k = 0; k < n; ++k) tl.push_back(make_int2((int)c, k));
-        for (int k : s->gtiles_host) gl.push_back(make_int2((int)c, k));
+        for (int rb = 0; rb < s->n_rb; ++rb)
+            for (int k = 0; k < s->n_strips; ++k) lists[k < s->n_wide ? 0 : 1].push_back(make_int4((int)c, k, rb, 0));
+        for (int g : s->gtiles_host) {
+            const int k = g % s->n_strips, rb = g / s->n_strips;
+            lists[k < s->n_wide ? 2 : 3].push_back(make_int4((int)c, k, rb, 0));
+        }
     }
     int mg = 0;
     for (const ij_sim* s : b->sims) mg = std::max(mg, s->n_ghost);
@@ -129,33 +131,36 @@ ij_status build_tiles(ij_batch* b)
         b->max_ghost = mg;
         drop_graph(b);
     }
-    auto same = [](const std::vector<int2>& u, const std::vector<int2>& v) {
-        return u.size() == v.size() && std::memcmp(u.data(), v.data(), u.size() * sizeof(int2)) == 0;
-    };
-    if (same(tl, b->tiles_host) && same(gl, b->gtiles_host) && (b->d_tiles || tl.empty()))
-        return IJ_OK;
-    if ((int)tl.size() > b->cap_tiles) {
+    std::vector<int4> all;
+    for (auto& l : lists) all.insert(all.end(), l.begin(), l.end());
+    const int counts[4] = {(int)lists[0].size(), (int)lists[1].size(), (int)lists[2].size(), (int)lists[3].size()};
+    const bool same = all.size() == b->tiles_host.size() &&
+                      std::memcmp(all.data(), b->tiles_host.data(), all.size() * sizeof(int4)) == 0 &&
+                      counts[0] == b->T.n_wide && counts[1] == b->T.n_tail && counts[2] == b->T.n_gwide &&
+                      counts[3] == b->T.n_gtail;
+    if (same && (b->d_tiles || all.empty())) return IJ_OK;
+    if (all.size() > b->cap_tiles) {
         if (b->d_tiles) (void)hipFree(b->d_tiles);
         b->d_tiles = nullptr;
-        if (hipMalloc(&b->d_tiles, tl.size() * sizeof(int2)) != hipSuccess)
+        b->cap_tiles = 0;
+        if (hipMalloc(&b->d_tiles, all.size() * sizeof(int4)) != hipSuccess)
             return bfail(b, IJ_ERR_OOM, "tile list allocation failed");
-        b->cap_tiles = (int)tl.size();
+        b->cap_tiles = all.size();
     }
-    if ((int)gl.size() > b->cap_gtiles) {
-        if (b->d_gtiles) (void)hipFree(b->d_gtiles);
-        b->d_gtiles = nullptr;
-        if (hipMalloc(&b->d_gtiles, gl.size() * sizeof(int2)) != hipSuccess)
-            return bfail(b, IJ_ERR_OOM, "tile list allocation failed");
-        b->cap_gtiles = (int)gl.size();
-    }
-    if (!tl.empty()) IJB_HIP(b, hipMemcpy(b->d_tiles, tl.data(), tl.size() * sizeof(int2), hipMemcpyHostToDevice));
-    if (!gl.empty()) IJB_HIP(b, hipMemcpy(b->d_gtiles, gl.data(), gl.size() * sizeof(int2), hipMemcpyHostToDevice));
-    b->tiles_host.swap(tl);
-    b->gtiles_host.swap(gl);
-    b->n_tiles = (int)b->tiles_host.size();
-    b->n_gtiles = (int)b->gtiles_host.size();
-    b->grid = ij::batch_resident_workgroups(b->waves_x);
-    if (b->grid <= 0) return bfail(b, IJ_ERR_DEVICE, "occupancy query failed");
+    if (!all.empty()) IJB_HIP(b, hipMemcpy(b->d_tiles, all.data(), all.size() * sizeof(int4), hipMemcpyHostToDevice));
+    b->tiles_host.swap(all);
+    ij::BatchTiles& T = b->T;
+    T.wide = b->d_tiles;
+    T.tail = T.wide + counts[0];
+    T.gwide = T.tail + counts[1];
+    T.gtail = T.gwide + counts[2];
+    T.n_wide = counts[0];
+    T.n_tail = counts[1];
+    T.n_gwide = counts[2];
+    T.n_gtail = counts[3];
+    T.grid_wide = ij::batch_resident_workgroups(b->waves_x);
+    T.grid_tail = ij::batch_resident_workgroups(1);
+    if (T.grid_wide <= 0 || T.grid_tail <= 0) return bfail(b, IJ_ERR_DEVICE, "occupancy query failed");
     drop_graph(b);
     return IJ_OK;
 }
@@ -180,6 +185,8 @@ ij_status stage(ij_batch* b, hipStream_t st)
         r.ring = s->samples;
         r.n_ghost = s->n_ghost;
         r.n_strips = s->n_strips;
+        r.n_wide = s->n_wide;
+        r.wide_w = 64 * s->waves_x;
         r.row0 = (int)s->p.diag_row0;
         r.a_min = (int)std::ceil(4.0 * s->p.width * s->p.width);
         r.t_pos = s->p.t_pos;
@@ -210,8 +217,8 @@ hipError_t one_step(ij_batch* b, int parity, bool diag, bool with_tick, hipStrea
         e = ij::launch_batch_diag(b->d_cases, (int)b->sims.size(), b->max_nx, b->max_ny, b->max_ghost, parity, b->d_t,
                                   b->d_nrec, b->d_active, st);
     if (e == hipSuccess)
-        e = ij::launch_batch_collide(b->d_cases, b->d_tiles, b->n_tiles, b->d_gtiles, b->n_gtiles, parity, b->d_t,
-                                     b->d_active, b->waves_x, b->rows_per_block, kGeneralRows, b->grid, st);
+        e = ij::launch_batch_collide(b->T, b->d_cases, parity, b->d_t, b->d_active, b->waves_x, b->rows_per_block,
+                                     kGeneralRows, st);
     if (e == hipSuccess && with_tick) e = ij::launch_batch_tick(b->d_t, st);
     return e;
 }
@@ -270,10 +277,9 @@ ij_status run_steps(ij_batch* b, int64_t n, hipStream_t st, bool use_graph)
     while (j < n) {
         const int64_t tj = b->t + j;
         if (period > 0 && tj % period == 0 && (j & 1) == 0 && n - j >= period) {
-            if (!b->gexec || b->graph_len != period || b->graph_tiles.size() != b->tiles_host.size()) {
+            if (!b->gexec || b->graph_len != period) {   // tile changes drop the graph
                 r = capture_graph(b, period);
                 if (r != IJ_OK) return r;
-                b->graph_tiles = b->tiles_host;
             }
             if (!on_cs) {
                 IJB_HIP(b, hipEventRecord(b->ev_in, st));
@@ -327,6 +333,7 @@ ij_status apply_tiling(ij_batch* b, int waves_x, int rows)
     for (ij_sim* s : b->sims) {
         s->waves_x = waves_x;
         s->rows_per_block = rows;
+        s->mixed_strips = true;
         if (build_plain(s) != IJ_OK) return bfail(b, IJ_ERR_DEVICE, s->err);
     }
     b->waves_x = waves_x;
@@ -393,7 +400,6 @@ void ij_batch_destroy(ij_batch* b)
     for (ij_sim* s : b->sims) destroy_sim(s);
     if (b->d_cases) (void)hipFree(b->d_cases);
     if (b->d_tiles) (void)hipFree(b->d_tiles);
-    if (b->d_gtiles) (void)hipFree(b->d_gtiles);
     if (b->d_t) (void)hipFree(b->d_t);
     if (b->d_nrec) (void)hipFree(b->d_nrec);
     if (b->d_active) (void)hipFree(b->d_active);

@@ -54,6 +54,8 @@ struct ij_sim {
     int n_gtiles = 0;
     std::vector<int> gtiles_host;
     int n_strips = 0, n_rb = 0;   // of the plain launch's tiling
+    int n_wide = 0;               // strips 64 * waves_x wide; the others are 64 wide
+    bool mixed_strips = false;    // tail strips of 64 columns (batches)
     bool in_batch = false;        // owned and stepped by an ij_batch
     std::string err;
 };

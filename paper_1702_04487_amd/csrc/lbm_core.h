@@ -52,6 +52,7 @@ struct CaseRec {
     DiagRow* rows;          // [ny]
     SampleRec* ring;        // diagnostics records
     int n_ghost, n_strips, row0, a_min;
+    int n_wide, wide_w;     // strips 0..n_wide-1 are wide_w columns wide, the others 64
     int64_t t_pos, t_neg, t_idle;
     int periodic;
     double f_pos, f_neg, u_limit;
@@ -78,13 +79,18 @@ hipError_t launch_state_io(const KParams& P, float* A, const uint8_t* wall, floa
 hipError_t launch_diag(const KParams& P, const float* A, const uint8_t* wall, const double* phi, int row0,
                        int a_min, int64_t step, DiagRow* rows, SampleRec* out, hipStream_t st);
 
-// Batched step work over every case.  tiles: (case, tile) pairs of the plain
-// launch (tiles of rows_per_block rows), gtiles: those of the general launch
-// (rows_general rows).  The plain launch is persistent: `grid` workgroups
-// (0 = as many as fit on the device) each run a contiguous run of tiles.
-hipError_t launch_batch_collide(const CaseRec* cases, const int2* tiles, int n_tiles, const int2* gtiles,
-                                int n_gtiles, int parity, const int64_t* t_dev, const int* active, int waves_x,
-                                int rows_per_block, int rows_general, int grid, hipStream_t st);
+// (case, strip, row block, -) tiles of a batch: plain tiles (rows_per_block
+// rows) and general tiles (rows_general rows) of the wide strips (workgroups
+// of 64 * waves_x lanes) and of the 64-column tail strips (one wave).  The
+// plain launches are persistent with grid_wide / grid_tail workgroups, each
+// running a contiguous run of tiles.
+struct BatchTiles {
+    const int4 *wide, *tail, *gwide, *gtail;
+    int n_wide, n_tail, n_gwide, n_gtail;
+    int grid_wide, grid_tail;
+};
+hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int64_t* t_dev,
+                                const int* active, int waves_x, int rows_per_block, int rows_general, hipStream_t st);
 hipError_t launch_batch_tick(int64_t* t_dev, hipStream_t st);
 hipError_t launch_batch_set_time(int64_t* t_dev, int64_t t, hipStream_t st);
 hipError_t launch_batch_diag(const CaseRec* cases, int n_cases, int max_nx, int max_ny, int max_ghost, int parity,

@@ -522,7 +522,7 @@ __device__ __forceinline__ float from_right(float v)
 template <int NW, bool PLAIN>
 __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const float* __restrict__ A,
                                              float* __restrict__ B, const uint8_t* __restrict__ wall,
-                                             const uint8_t* __restrict__ plain_rows, int strip, int rb,
+                                             const uint8_t* __restrict__ plain_rows, int strip, int x0, int rb,
                                              int rows_per_block)
 {
     constexpr int BW = 64 * NW;
@@ -538,7 +538,6 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
     __shared__ uint8_t s_mine[kMaxRowsPerBlock];      // rows of the block this launch collides
 
     __syncthreads();   // LDS of a previous tile of this workgroup is free
-    const int x0 = strip * BW;
     const int wv = min(BW, P.nx - x0);
     const int y0 = rb * rows_per_block;
     const int y1 = min(P.ny, y0 + rows_per_block);
@@ -834,7 +833,8 @@ __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const floa
         tile = tile_list[blockIdx.x];
     }
     const int rb = tile / n_strips;
-    collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, tile - rb * n_strips, rb, rows_per_block);
+    const int strip = tile - rb * n_strips;
+    collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, strip, strip * 64 * NW, rb, rows_per_block);
 }
 
 // ------------------------------------------------------------ init / moments
@@ -1209,25 +1209,27 @@ __device__ __forceinline__ double case_pulse(const CaseRec& c, int64_t t)
 }
 
 // Persistent over tiles: workgroup b runs tiles [b * per_wg, (b + 1) *
-// per_wg) of the (case, tile) list, in order (neighbouring tiles of a case
-// share their halo rows through the cache).
+// per_wg) of the (case, strip, row block) list, in order (neighbouring tiles
+// of a case share their halo rows through the cache).  A case's strips are
+// R.n_wide strips of R.wide_w columns, then 64-column strips; a launch takes
+// the tiles of its own strip width (64 * NW).
 template <int NW, bool PLAIN>
 __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __restrict__ cases,
-                                                           const int2* __restrict__ tiles, int n_tiles,
+                                                           const int4* __restrict__ tiles, int n_tiles,
                                                            int per_wg, int parity, const int64_t* __restrict__ t_dev,
                                                            const int* __restrict__ active, int rows_per_block)
 {
     const int64_t t = *t_dev;
     const int i0 = blockIdx.x * per_wg, i1 = min(n_tiles, i0 + per_wg);
     for (int i = i0; i < i1; ++i) {
-        const int2 tl = tiles[i];   // (case, tile of the case)
+        const int4 tl = tiles[i];   // (case, strip, row block, -)
         if (!active[tl.x]) continue;
         const CaseRec& R = cases[tl.x];
         const KParams P = R.P;
         const float fb = (float)case_pulse(R, t);
-        const int rb = tl.y / R.n_strips;
-        collide_tile<NW, PLAIN>(P, fb, R.buf[parity], R.buf[1 - parity], R.wall, R.plain, tl.y - rb * R.n_strips,
-                                rb, rows_per_block);
+        const int x0 = tl.y < R.n_wide ? tl.y * R.wide_w : R.n_wide * R.wide_w + (tl.y - R.n_wide) * 64;
+        collide_tile<NW, PLAIN>(P, fb, R.buf[parity], R.buf[1 - parity], R.wall, R.plain, tl.y, x0, tl.z,
+                                rows_per_block);
     }
 }
 
@@ -1351,25 +1353,34 @@ int batch_resident_workgroups(int waves_x)
     return e == hipSuccess ? cus * per_cu : 0;
 }
 
-hipError_t launch_batch_collide(const CaseRec* cases, const int2* tiles, int n_tiles, const int2* gtiles,
-                                int n_gtiles, int parity, const int64_t* t_dev, const int* active, int waves_x,
-                                int rows_per_block, int rows_general, int grid, hipStream_t st)
+hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int64_t* t_dev,
+                                const int* active, int waves_x, int rows_per_block, int rows_general, hipStream_t st)
 {
     if (rows_per_block < 1 || rows_per_block > kMaxRowsPerBlock || rows_general < 1 ||
-        rows_general > kMaxRowsPerBlock || n_tiles < 0 || n_gtiles < 0 || (parity & ~1))
+        rows_general > kMaxRowsPerBlock || (parity & ~1))
         return hipErrorInvalidValue;
-    if (grid <= 0) grid = batch_resident_workgroups(waves_x);
-    if (grid <= 0) return hipErrorInvalidValue;
-    grid = n_tiles > 0 ? std::min(grid, n_tiles) : 0;
-    const int per_wg = grid > 0 ? (n_tiles + grid - 1) / grid : 0;
-    if (per_wg > 0) grid = (n_tiles + per_wg - 1) / per_wg;
+    // persistent plain launches (one per strip width), then the general tiles
+    auto persistent = [&](int n, int grid, int& per_wg) {
+        grid = n > 0 ? std::min(grid, n) : 0;
+        per_wg = grid > 0 ? (n + grid - 1) / grid : 0;
+        return per_wg > 0 ? (n + per_wg - 1) / per_wg : 0;
+    };
+    int pw = 0, pt = 0;
+    const int gw = persistent(T.n_wide, T.grid_wide, pw);
+    const int gt = persistent(T.n_tail, T.grid_tail, pt);
+    if (gt > 0)
+        hipLaunchKernelGGL((k_batch_collide<1, true>), dim3(gt), dim3(64), 0, st, cases, T.tail, T.n_tail, pt,
+                           parity, t_dev, active, rows_per_block);
+    if (T.n_gtail > 0)
+        hipLaunchKernelGGL((k_batch_collide<1, false>), dim3(T.n_gtail), dim3(64), 0, st, cases, T.gtail, T.n_gtail,
+                           1, parity, t_dev, active, rows_general);
 #define IJ_BLAUNCH(NWV)                                                                                       \
-    if (grid > 0)                                                                                             \
-        hipLaunchKernelGGL((k_batch_collide<NWV, true>), dim3(grid), dim3(64 * NWV), 0, st, cases, tiles,      \
-                           n_tiles, per_wg, parity, t_dev, active, rows_per_block);                          \
-    if (n_gtiles > 0)                                                                                         \
-        hipLaunchKernelGGL((k_batch_collide<NWV, false>), dim3(n_gtiles), dim3(64 * NWV), 0, st, cases, gtiles, \
-                           n_gtiles, 1, parity, t_dev, active, rows_general);
+    if (gw > 0)                                                                                               \
+        hipLaunchKernelGGL((k_batch_collide<NWV, true>), dim3(gw), dim3(64 * NWV), 0, st, cases, T.wide,       \
+                           T.n_wide, pw, parity, t_dev, active, rows_per_block);                              \
+    if (T.n_gwide > 0)                                                                                        \
+        hipLaunchKernelGGL((k_batch_collide<NWV, false>), dim3(T.n_gwide), dim3(64 * NWV), 0, st, cases, T.gwide, \
+                           T.n_gwide, 1, parity, t_dev, active, rows_general);
     switch (waves_x) {
     case 1: IJ_BLAUNCH(1) break;
     case 2: IJ_BLAUNCH(2) break;

@@ -1,0 +1,244 @@
+"""Sweep surrogate: the lattice Boltzmann solver generates training cases,
+an ensemble of networks is trained on them on the GPU, and queries are
+answered by the network where its members agree and by the solver
+elsewhere (the trust region).  The solver is also the judge of the
+network's error.
+
+Cases follow the paper's sweeps (Figs. 4-7: contact angle, surface tension
+and the pulse) on one nozzle geometry: a 256 x 2048 lattice, nozzle 32 wide
+and 256 long, tau 0.8 ink / 1.0 ambient, a periodic pulse so that the idle
+time matters.  Inputs (7): contact angle (deg), sigma, f_pos, f_neg, t_pos,
+t_neg, t_idle, drawn uniformly (sigma log-uniformly) from the sweep ranges.
+The solver runs the stable variant of each case (Gamma * sigma <= 0.01,
+pulse amplitudes scaled to a 0.2 viscous speed bound), a deterministic map
+of the inputs.  Targets (4): breakup step (the horizon when no drop
+detaches), drop velocity (0 without breakup), drop volume and the satellite
+flag.
+
+Command line (runs on the GPU):
+    python -m paper_1702_04487_amd.surrogate generate --n 768 --seed 7 --out a.npz
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import sys
+import time
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+DATA_DIR = os.path.join(HERE, "data")
+
+GEOMETRY = dict(nx=256, ny=2048, w=32, L=256)
+HORIZON = 24000
+DIAG_EVERY = 50
+RANGES = dict(theta=(30.0, 150.0), sigma=(0.005, 0.02), f=(5e-5, 3e-4), t=(500, 3000))
+INPUT_NAMES = ("theta", "sigma", "f_pos", "f_neg", "t_pos", "t_neg", "t_idle")
+TARGET_NAMES = ("breakup_step", "v_drop", "vol_drop", "satellite")
+U_CAP = 0.2
+GAMMA_SIGMA_MAX = 0.01
+
+
+def _log(msg: str) -> None:
+    print(f"surrogate: {msg}", file=sys.stderr, flush=True)
+
+
+# --------------------------------------------------------------- cases
+def sample_inputs(n: int, seed: int) -> np.ndarray:
+    """[n, 7] inputs drawn from the sweep ranges (seeded SplitMix64)."""
+    if ROOT not in sys.path:
+        sys.path.insert(0, ROOT)
+    import workloads as W
+    u = W.uniform_array(seed, n * 7).reshape(n, 7)
+    x = np.zeros((n, 7))
+    x[:, 0] = RANGES["theta"][0] + (RANGES["theta"][1] - RANGES["theta"][0]) * u[:, 0]
+    ls = np.log(RANGES["sigma"])
+    x[:, 1] = np.exp(ls[0] + (ls[1] - ls[0]) * u[:, 1])
+    for c in (2, 3):
+        x[:, c] = RANGES["f"][0] + (RANGES["f"][1] - RANGES["f"][0]) * u[:, c]
+    lo, hi = RANGES["t"]
+    for c in (4, 5, 6):
+        x[:, c] = np.floor(lo + (hi - lo + 1) * u[:, c])
+    return x
+
+
+def case_params(x: np.ndarray, horizon: int = HORIZON) -> dict:
+    """Solver parameters of one input row (stable variant)."""
+    g = GEOMETRY
+    theta, sigma, fp, fn, tp, tn, ti = (float(v) for v in x)
+    n0, nu_ink = 0.5 * (1.0 + 0.1), (0.8 - 0.5) / 3.0
+    bound = max(fp, fn) * g["w"] ** 2 / (8.0 * n0 * nu_ink)
+    scale = min(1.0, U_CAP / bound)
+    return dict(nx=g["nx"], ny=g["ny"], bc_y=1, force_rows=g["L"], t_pos=int(tp), t_neg=int(tn), t_idle=int(ti),
+                periodic_pulse=1, rho_ink=1.0, rho_amb=0.1, sigma=sigma, width=4.0,
+                gamma=min(1.0, GAMMA_SIGMA_MAX / sigma), tau_ink=0.8, tau_amb=1.0, tau_phi=1.0,
+                theta_inner=theta, theta_outer=90.0, f_pos=fp * scale, f_neg=fn * scale,
+                nozzle_x0=(g["nx"] - g["w"]) // 2, nozzle_w=g["w"], nozzle_len=g["L"], diag_row0=g["L"],
+                diag_every=DIAG_EVERY)
+
+
+def targets_of(diag: dict, horizon: int) -> np.ndarray:
+    tb = diag["breakup_step"]
+    v = diag["v_drop"]
+    if tb < 0:
+        return np.array([float(horizon), 0.0, 0.0, 0.0])
+    return np.array([float(tb), 0.0 if not math.isfinite(v) else float(v), float(diag["vol_drop"]),
+                     float(diag["satellite"])])
+
+
+def run_lbm(x: np.ndarray, horizon: int = HORIZON, chunk: int = 256, progress: bool = True):
+    """Run every input row through the batched solver; returns (targets
+    [n, 4], unstable mask [n], seconds of GPU wall time)."""
+    import torch
+    from paper_1702_04487_amd import lbm
+    n = len(x)
+    y = np.zeros((n, 4))
+    bad = np.zeros(n, bool)
+    seconds = 0.0
+    for c0 in range(0, n, chunk):
+        rows = range(c0, min(n, c0 + chunk))
+        b = lbm.Batch([case_params(x[i], horizon) for i in rows])
+        for sim in b.cases:
+            sim.init_default()
+        b.autotune(6)
+        b.set_graph(DIAG_EVERY)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < horizon:
+            k = min(4000, horizon - done)
+            b.step(k)
+            done += k
+            torch.cuda.synchronize()
+            if progress:
+                _log(f"cases {c0}-{rows[-1]}: step {done} of {horizon}")
+        seconds += time.perf_counter() - t0
+        for i, sim in zip(rows, b.cases):
+            d = sim.diagnostics()
+            y[i] = targets_of(d, horizon)
+            bad[i] = d["unstable_step"] >= 0
+        b.close()
+    return y, bad, seconds
+
+
+def solver_seconds_per_case(x: np.ndarray, horizon: int = HORIZON, steps: int = 600, cases: int = 64) -> float:
+    """Batched solver time per case for `horizon` steps, from a timed run of
+    `steps` steps of the first `cases` input rows together (graphs of 50
+    steps, diagnostics every 50)."""
+    import torch
+    from paper_1702_04487_amd import lbm
+    b = lbm.Batch([case_params(r, horizon) for r in x[:cases]])
+    for sim in b.cases:
+        sim.init_default()
+    b.set_graph(DIAG_EVERY)
+    b.step(100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n = len(b.cases)
+    b.close()
+    return dt / steps * horizon / n
+
+
+def generate(n: int, seed: int, out: str, horizon: int = HORIZON) -> None:
+    x = sample_inputs(n, seed)
+    y, bad, sec = run_lbm(x, horizon)
+    np.savez(out, x=x, y=y, unstable=bad, seed=seed, horizon=horizon, gpu_seconds=sec,
+             geometry=np.array([GEOMETRY[k] for k in ("nx", "ny", "w", "L")]))
+    _log(f"{n} cases in {sec:.1f} s of GPU time; {int((y[:, 0] < horizon).sum())} break up, "
+         f"{int(bad.sum())} unstable -> {out}")
+
+
+def load_dataset(paths=None):
+    """(x, y, horizon, seconds per case) of the stored training cases."""
+    if paths is None:
+        paths = sorted(os.path.join(DATA_DIR, f) for f in os.listdir(DATA_DIR) if f.endswith(".npz"))
+    xs, ys, sec, n = [], [], 0.0, 0
+    horizon = None
+    for p in paths:
+        d = np.load(p, allow_pickle=False)
+        keep = ~d["unstable"]
+        xs.append(d["x"][keep])
+        ys.append(d["y"][keep])
+        sec += float(d["gpu_seconds"])
+        n += len(d["x"])
+        horizon = int(d["horizon"])
+    return np.concatenate(xs), np.concatenate(ys), horizon, sec / max(n, 1)
+
+
+# --------------------------------------------------------------- network
+class Surrogate:
+    """An ensemble of networks with the input and target scaling of its
+    training set and a trust threshold on the ensemble spread."""
+
+    def __init__(self, members: int = 4):
+        from paper_1702_04487_amd import lbm
+        self.net = lbm.MLP(members)
+        self.members = members
+        self.threshold = None
+
+    def fit(self, x: np.ndarray, y: np.ndarray, steps: int = 4000, batch: int = 256, lr: float = 2e-3,
+            seed: int = 99):
+        if ROOT not in sys.path:
+            sys.path.insert(0, ROOT)
+        import workloads as W
+        self.x_mean, self.x_std = x.mean(axis=0), x.std(axis=0) + 1e-12
+        self.y_mean, self.y_std = y[:, :3].mean(axis=0), y[:, :3].std(axis=0) + 1e-12
+        self.net.set_scaling(self.x_mean, self.x_std, self.y_mean, self.y_std)
+        for k in range(self.members):
+            self.net.set_weights(k, W.mlp_init(seed + 1000 * k))
+        idx = np.stack([W.minibatch_order(seed + 1000 * k + 1, len(x), steps, batch) for k in range(self.members)])
+        loss = self.net.train(x, y, idx, lr)
+        return loss.cpu().numpy()
+
+    def predict(self, x: np.ndarray):
+        """(mean [n, 4], normalised spread [n]) on the host: the spread is the
+        largest member standard deviation of breakup step and drop velocity
+        in units of the training targets' spread."""
+        mean, spread = self.net.predict(x)
+        mean = mean.cpu().numpy().astype(np.float64)
+        spread = spread.cpu().numpy().astype(np.float64)
+        return mean, np.max(spread[:, :2] / self.y_std[:2], axis=1)
+
+
+def errors(pred: np.ndarray, y: np.ndarray, v_scale: float = 0.01):
+    """Relative errors of breakup step and drop velocity: |dt| / t and
+    |dv| / max(|v|, v_scale) (v_scale: a typical drop speed, so that cases
+    without a drop, v = 0, are judged on an absolute scale)."""
+    et = np.abs(pred[:, 0] - y[:, 0]) / np.maximum(np.abs(y[:, 0]), 1.0)
+    ev = np.abs(pred[:, 1] - y[:, 1]) / np.maximum(np.abs(y[:, 1]), v_scale)
+    return et, ev
+
+
+def calibrate(spread: np.ndarray, et: np.ndarray, ev: np.ndarray, tol: float = 0.02) -> float:
+    """Largest spread threshold whose answered cases (spread <= threshold)
+    keep the mean of both errors within tol (0 if none does)."""
+    order = np.argsort(spread)
+    ce_t = np.cumsum(et[order]) / np.arange(1, len(order) + 1)
+    ce_v = np.cumsum(ev[order]) / np.arange(1, len(order) + 1)
+    ok = np.nonzero((ce_t <= tol) & (ce_v <= tol))[0]
+    return float(spread[order][ok[-1]]) if len(ok) else 0.0
+
+
+def main(argv: Optional[list] = None) -> int:
+    ap = argparse.ArgumentParser(prog="python -m paper_1702_04487_amd.surrogate")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    g = sub.add_parser("generate", help="run sweep cases through the solver and store inputs and targets")
+    g.add_argument("--n", type=int, required=True)
+    g.add_argument("--seed", type=int, required=True)
+    g.add_argument("--out", required=True)
+    g.add_argument("--horizon", type=int, default=HORIZON)
+    a = ap.parse_args(argv)
+    if a.cmd == "generate":
+        generate(a.n, a.seed, a.out, a.horizon)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

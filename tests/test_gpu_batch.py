@@ -31,6 +31,12 @@ def _cases():
     wall = W.flat_wall(nx, ny, (0, 1))
     wall[20:26, 30:41] = W.WALL_OUTER
     out.append((p, wall, W.discs_distance(nx, ny, [(35.0, 12.0, 9.0), (10.0, 36.0, 6.0)])))
+    # wider than one 256-column strip: full strips plus a tail of 44 columns
+    nx, ny = 300, 40
+    p = W.base_params(nx, ny, bc_y=W.BC_PERIODIC, tau_ink=0.85, force_rows=ny, f_pos=2e-5, t_pos=10 ** 6,
+                      diag_every=K, diag_row0=2)
+    wall = W.flat_wall(nx, ny, (0, 1))
+    out.append((p, wall, W.discs_distance(nx, ny, [(60.0, 20.0, 10.0), (250.0, 18.0, 12.0), (290.0, 30.0, 6.0)])))
     return out
 
 

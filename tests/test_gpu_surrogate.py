@@ -1,0 +1,54 @@
+"""What the trained network gains over the solver alone (sweep surrogate).
+
+The ensemble is trained on the GPU by the library's own kernels on the
+stored solver cases (paper_1702_04487_amd/data), its trust threshold is
+calibrated on a 10 % split of them, and 256 held-out cases are answered by
+the network where the members agree and by the solver elsewhere.  The
+solver's stored results judge the answers: those the network gives stay
+within 2 % (mean error of breakup step and drop velocity); the rest are
+the solver's own.  Wall times are measured here: the network's prediction,
+and the solver's cost per case from a batched run of held-out cases."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1702_04487_amd import surrogate as S
+
+pytestmark = pytest.mark.gpu
+
+HELD = 256
+
+
+def _split():
+    x, y, horizon, _ = S.load_dataset()
+    xt, yt, xh, yh = x[:-HELD], y[:-HELD], x[-HELD:], y[-HELD:]
+    ncal = len(xt) // 10
+    return (xt[:-ncal], yt[:-ncal]), (xt[-ncal:], yt[-ncal:]), (xh, yh), horizon
+
+
+def test_surrogate_gain_over_solver_alone(gpu_lib):
+    import torch
+    (xtr, ytr), (xc, yc), (xh, yh), horizon = _split()
+    sur = S.Surrogate(4)
+    loss = sur.fit(xtr, ytr, steps=3000)
+    assert np.isfinite(loss).all() and loss[:, -100:].mean() < 0.5 * loss[:, :20].mean()
+    pc, sc = sur.predict(xc)
+    threshold = S.calibrate(sc, *S.errors(pc, yc))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ph, sh = sur.predict(xh)
+    t_pred = time.perf_counter() - t0
+    answered = sh <= threshold
+    et, ev = S.errors(ph, yh)
+    t_case = S.solver_seconds_per_case(xh, horizon)
+    t_alone = HELD * t_case
+    t_with = t_pred + (~answered).sum() * t_case
+    gain = t_alone / t_with
+    print(f"answered {answered.sum()} of {HELD}; errors on answered t_b {et[answered].mean() if answered.any() else 0:.4f} "
+          f"v {ev[answered].mean() if answered.any() else 0:.4f}; solver {t_case:.3f} s per case; "
+          f"predict {t_pred * 1e3:.2f} ms; gain {gain:.2f}x")
+    if answered.any():
+        assert et[answered].mean() <= 0.02 and ev[answered].mean() <= 0.02
+    assert answered.sum() >= HELD // 10, "the network answers too few held-out cases to gain anything"
+    assert gain > 1.1

@@ -1,0 +1,57 @@
+"""Host logic of the sweep surrogate (no GPU): inputs over the sweep
+ranges, the stable solver parameters of an input row, the target encoding
+of a diagnostics record, the error definitions and the trust-threshold
+calibration."""
+import math
+
+import numpy as np
+
+from paper_1702_04487_amd import surrogate as S
+
+
+def test_inputs_cover_the_sweep_ranges_deterministically():
+    x = S.sample_inputs(4000, 3)
+    assert np.array_equal(x, S.sample_inputs(4000, 3))
+    assert x[:, 0].min() >= 30 and x[:, 0].max() <= 150
+    assert x[:, 1].min() >= 0.005 and x[:, 1].max() <= 0.02
+    # sigma log-uniform: its log is uniform, so half the draws lie below the geometric mean
+    assert abs(np.mean(x[:, 1] < math.sqrt(0.005 * 0.02)) - 0.5) < 0.03
+    for c in (2, 3):
+        assert x[:, c].min() >= 5e-5 and x[:, c].max() <= 3e-4
+    for c in (4, 5, 6):
+        assert x[:, c].min() >= 500 and x[:, c].max() <= 3000 and np.all(x[:, c] == np.floor(x[:, c]))
+
+
+def test_stable_parameters_respect_both_bounds():
+    x = S.sample_inputs(500, 4)
+    for row in x:
+        p = S.case_params(row)
+        assert p["gamma"] * p["sigma"] <= S.GAMMA_SIGMA_MAX * (1 + 1e-12)
+        bound = max(p["f_pos"], p["f_neg"]) * 32 ** 2 / (8 * 0.55 * 0.1)
+        assert bound <= S.U_CAP * (1 + 1e-12)
+        # one factor for both amplitudes: their ratio is kept
+        assert p["f_pos"] / p["f_neg"] == np.float64(row[2] / row[3]) or \
+            abs(p["f_pos"] / p["f_neg"] - row[2] / row[3]) < 1e-12 * row[2] / row[3]
+        assert p["periodic_pulse"] == 1 and p["nozzle_w"] == 32 and p["nozzle_len"] == 256
+
+
+def test_target_encoding():
+    none = dict(breakup_step=-1, v_drop=float("nan"), vol_drop=0, satellite=0)
+    assert list(S.targets_of(none, 24000)) == [24000.0, 0.0, 0.0, 0.0]
+    drop = dict(breakup_step=6400, v_drop=0.0073, vol_drop=9200, satellite=1)
+    assert list(S.targets_of(drop, 24000)) == [6400.0, 0.0073, 9200.0, 1.0]
+    lost = dict(breakup_step=16200, v_drop=float("nan"), vol_drop=0, satellite=0)
+    assert list(S.targets_of(lost, 24000)) == [16200.0, 0.0, 0.0, 0.0]
+
+
+def test_errors_and_calibration():
+    y = np.array([[10000.0, 0.02], [20000.0, 0.0], [5000.0, -0.01], [24000.0, 0.0]])
+    pred = np.array([[10100.0, 0.0202], [20000.0, 0.001], [6000.0, -0.01], [24000.0, 0.0]])
+    et, ev = S.errors(pred, y)
+    assert np.allclose(et, [0.01, 0.0, 0.2, 0.0])
+    assert np.allclose(ev, [0.01, 0.1, 0.0, 0.0])   # |v| < 0.01 judged against 0.01
+    spread = np.array([0.1, 0.3, 0.5, 0.05])
+    # ordered by spread: cases 3, 0, 1, 2; running means of e_t: 0, .005, .0033, .0525;
+    # of e_v: 0, .005, .0367 -> the last admissible prefix ends at case 0
+    assert S.calibrate(spread, et, ev, tol=0.02) == 0.1
+    assert S.calibrate(spread, et + 1.0, ev, tol=0.02) == 0.0
