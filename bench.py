@@ -41,9 +41,9 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1702_04487_amd", "csrc", "lbm_core.hip
 # (2.000 for FETCH_SIZE, 1.000 for WRITE_SIZE).  The figure holds for the
 # kernel source with this SHA-256 only; for any other it is reported as null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "5157fae1b19366ddaa3ad9045922c8dcbfd9f638ad737d85cd04f8ad50ce4661",
-    "read_bytes": 2117275685,
-    "write_bytes": 1978553174,
+    "kernel_source_sha256": "577257459e70815a1d854f837818921621bb26c31e19ad4508d5876520e52c09",
+    "read_bytes": 2118334563,
+    "write_bytes": 1978625979,
 }
 COPY_CEILING_GBS = 5148.4  # best read+write rate of copy_calib on MI355X (float4, 65536 x 256)
 
@@ -111,8 +111,9 @@ def sweep_bench(batched_steps: int = 600, plain_steps: int = 300, plain_every: i
     b = lbm.Batch([c["params"] for c in cases])
     for sim in b.cases:
         sim.init_default()
-    w, r, tune_ms = b.autotune(10)
-    log(f"sweep: autotuned tile {w} waves x {r} rows ({tune_ms:.3f} ms per step)")
+    w, r, mixed, persistent, tune_ms = b.autotune(10)
+    log(f"sweep: autotuned tile {w} waves x {r} rows, mixed strips {mixed}, persistent {persistent} "
+        f"({tune_ms:.3f} ms per step)")
     b.set_graph(50)
     b.step(100)
     ms_b = timed(lambda: b.step(batched_steps)) / batched_steps
@@ -140,7 +141,7 @@ def sweep_bench(batched_steps: int = 600, plain_steps: int = 300, plain_every: i
             "batched_over_plain": round(batched_cph / plain_cph, 2),
             "batched_ms_per_step": round(ms_b, 4), "batched_mlups": round(nodes / (ms_b * 1e-3) / 1e6, 1),
             "plain_ms_per_case_step": round(ms_p, 5),
-            "tile": [w, r], "graph_steps": 50, "unstable_cases": unstable,
+            "tile": [w, r], "mixed_strips": mixed, "persistent": persistent, "graph_steps": 50, "unstable_cases": unstable,
             "timed": {"batched_steps": batched_steps, "plain_cases": len(per_case), "plain_steps": plain_steps}}
 
 

@@ -260,19 +260,28 @@ ij_status ij_batch_step(ij_batch *b, int64_t nsteps, void *stream);
  * kernel.  Results are the same either way. */
 ij_status ij_batch_set_graph(ij_batch *b, int32_t steps_per_graph);
 
-/* Tile shape of every case: waves across x per workgroup (1, 2 or 4) and
- * rows per workgroup (1..1024). */
-ij_status ij_batch_set_tiling(ij_batch *b, int32_t waves_x, int32_t rows_per_block);
-ij_status ij_batch_get_tiling(const ij_batch *b, int32_t *waves_x, int32_t *rows_per_block);
+/* Tile shape of every case: waves across x per workgroup (1, 2 or 4), rows
+ * per workgroup (1..1024); mixed_strips: nonzero gives the columns past a
+ * case's last full strip of 64 * waves_x to 64-column strips (a second,
+ * one-wave launch) instead of a partly idle full-width strip; persistent:
+ * nonzero runs as many workgroups as are resident at once, each over a
+ * contiguous run of tiles, zero one workgroup per tile.  Default
+ * (4, 32, 0, 1). */
+ij_status ij_batch_set_tiling(ij_batch *b, int32_t waves_x, int32_t rows_per_block, int32_t mixed_strips,
+                              int32_t persistent);
+ij_status ij_batch_get_tiling(const ij_batch *b, int32_t *waves_x, int32_t *rows_per_block,
+                              int32_t *mixed_strips, int32_t *persistent);
 
 /* Autotuner: time trial_steps steps (2..10000) of the batch for each
- * candidate tile shape (1, 2, 4 waves x 16, 32, 64 rows) and keep the
- * fastest; the state of every case is restored afterwards (the step counter
- * does not move).  Results are cached for the process by the cases' sizes
- * and walls: a cached shape is applied without timing (*ms_per_step = -1).
- * Outputs may be NULL.  Synchronises the stream. */
+ * candidate tile shape (waves 1, 2, 4 x rows 32, 64, with and without mixed
+ * strips, persistent or not) and keep the fastest; the state of every case is restored
+ * afterwards (the step counter does not move).  Results are cached for the
+ * process by the cases' sizes and walls: a cached shape is applied without
+ * timing (*ms_per_step = -1).  Outputs may be NULL.  Synchronises the
+ * stream. */
 ij_status ij_batch_autotune(ij_batch *b, int32_t trial_steps, void *stream, int32_t *waves_x,
-                            int32_t *rows_per_block, double *ms_per_step);
+                            int32_t *rows_per_block, int32_t *mixed_strips, int32_t *persistent,
+                            double *ms_per_step);
 
 /* --------------------------------------------------------------- surrogate
  *

@@ -231,8 +231,18 @@ ij_status build_plain(ij_sim* s)
             plain[(size_t)k * ny + y] = ok ? 1 : 0;
         }
     }
-    // general tiles are short (kGeneralRows rows: few rows to collide, many
-    // workgroups) and numbered row-block major: tile = block * n_strips + strip
+    // general tiles, numbered row-block major (tile = block * n_strips +
+    // strip), are short (latency: a lone lattice leaves the device mostly
+    // idle) unless the lattice is one of a batch (throughput) and some strip
+    // has a long run of general rows
+    int longest = 0;
+    for (int k = 0; k < n_strips; ++k)
+        for (int y = 0, run = 0; y < ny; ++y) {
+            run = plain[(size_t)k * ny + y] ? 0 : run + 1;
+            longest = std::max(longest, run);
+        }
+    const int kGeneralRows = s->in_batch && longest >= kGeneralTallRun ? kGeneralRowsTall : kGeneralRowsShort;
+    s->rows_general = kGeneralRows;
     const int n_rb_g = (ny + kGeneralRows - 1) / kGeneralRows;
     for (int b = 0; b < n_rb_g; ++b)
         for (int k = 0; k < n_strips; ++k) {
@@ -501,7 +511,7 @@ ij_status ij_step(ij_sim* s, int64_t nsteps, void* stream)
         }
         s->K.fb = (float)pulse_value(s->p, s->t);
         hipError_t e = ij::launch_collide_fused(s->K, s->buf[s->cur], s->buf[1 - s->cur], s->wall, s->plain,
-                                                s->gtiles, s->n_gtiles, s->waves_x, s->rows_per_block, kGeneralRows,
+                                                s->gtiles, s->n_gtiles, s->waves_x, s->rows_per_block, s->rows_general,
                                                 st);
         if (e != hipSuccess) return hip_fail(s, e, "collide-stream kernel");
         s->cur = 1 - s->cur;

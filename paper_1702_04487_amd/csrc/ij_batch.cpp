@@ -20,19 +20,24 @@ namespace {
 
 thread_local std::string g_batch_create_error;
 
-// tile shapes the autotuner times (waves across x, rows per workgroup)
-const int kCandidates[][2] = {{1, 16}, {1, 32}, {2, 16}, {2, 32}, {2, 64}, {4, 16}, {4, 32}, {4, 64}};
+// tile shapes the autotuner times: waves across x, rows per workgroup, and
+// whether the columns past the last full strip go to 64-column strips; each
+// with persistent workgroups and with one workgroup per tile
+const int kCandidates[][3] = {{1, 32, 0}, {2, 32, 0}, {2, 64, 0}, {4, 32, 0}, {4, 64, 0}, {2, 64, 1}, {4, 64, 1}};
 
 // autotuned shapes by batch signature (lattice sizes, walls and diagnostics
 // interval of every case), for the life of the process
 std::mutex g_tune_mutex;
-std::map<std::vector<int64_t>, std::pair<int, int>> g_tune_cache;
+struct Tiling {
+    int waves_x, rows, mixed, persistent;
+};
+std::map<std::vector<int64_t>, Tiling> g_tune_cache;
 
 }  // namespace
 
 struct ij_batch {
     std::vector<ij_sim*> sims;
-    int waves_x = 4, rows_per_block = 32;
+    int waves_x = 4, rows_per_block = 32, mixed = 0, persistent = 1;
     int64_t t = 0;
     int64_t diag_every = 0;
     int graph_steps = 0;   // steps per captured graph, 0: plain launches
@@ -112,6 +117,23 @@ int64_t graph_period(const ij_batch* b)
     return (want + unit - 1) / unit * unit;
 }
 
+// workgroups of the two plain launches: as many as are resident at once
+// (each running a contiguous run of tiles), or one per tile
+ij_status set_grids(ij_batch* b)
+{
+    ij::BatchTiles& T = b->T;
+    int gw = T.n_wide, gt = T.n_tail;
+    if (b->persistent) {
+        gw = ij::batch_resident_workgroups(b->waves_x);
+        gt = ij::batch_resident_workgroups(1);
+        if (gw <= 0 || gt <= 0) return bfail(b, IJ_ERR_DEVICE, "occupancy query failed");
+    }
+    if (gw != T.grid_wide || gt != T.grid_tail) drop_graph(b);
+    T.grid_wide = gw;
+    T.grid_tail = gt;
+    return IJ_OK;
+}
+
 // tile lists of the launches from the members' current tilings
 ij_status build_tiles(ij_batch* b)
 {
@@ -138,7 +160,7 @@ ij_status build_tiles(ij_batch* b)
                       std::memcmp(all.data(), b->tiles_host.data(), all.size() * sizeof(int4)) == 0 &&
                       counts[0] == b->T.n_wide && counts[1] == b->T.n_tail && counts[2] == b->T.n_gwide &&
                       counts[3] == b->T.n_gtail;
-    if (same && (b->d_tiles || all.empty())) return IJ_OK;
+    if (same && (b->d_tiles || all.empty())) return set_grids(b);
     if (all.size() > b->cap_tiles) {
         if (b->d_tiles) (void)hipFree(b->d_tiles);
         b->d_tiles = nullptr;
@@ -158,11 +180,8 @@ ij_status build_tiles(ij_batch* b)
     T.n_tail = counts[1];
     T.n_gwide = counts[2];
     T.n_gtail = counts[3];
-    T.grid_wide = ij::batch_resident_workgroups(b->waves_x);
-    T.grid_tail = ij::batch_resident_workgroups(1);
-    if (T.grid_wide <= 0 || T.grid_tail <= 0) return bfail(b, IJ_ERR_DEVICE, "occupancy query failed");
     drop_graph(b);
-    return IJ_OK;
+    return set_grids(b);
 }
 
 // Case records, sample counters and guard flags of the current state, on
@@ -187,6 +206,7 @@ ij_status stage(ij_batch* b, hipStream_t st)
         r.n_strips = s->n_strips;
         r.n_wide = s->n_wide;
         r.wide_w = 64 * s->waves_x;
+        r.rows_general = s->rows_general;
         r.row0 = (int)s->p.diag_row0;
         r.a_min = (int)std::ceil(4.0 * s->p.width * s->p.width);
         r.t_pos = s->p.t_pos;
@@ -217,8 +237,7 @@ hipError_t one_step(ij_batch* b, int parity, bool diag, bool with_tick, hipStrea
         e = ij::launch_batch_diag(b->d_cases, (int)b->sims.size(), b->max_nx, b->max_ny, b->max_ghost, parity, b->d_t,
                                   b->d_nrec, b->d_active, st);
     if (e == hipSuccess)
-        e = ij::launch_batch_collide(b->T, b->d_cases, parity, b->d_t, b->d_active, b->waves_x, b->rows_per_block,
-                                     kGeneralRows, st);
+        e = ij::launch_batch_collide(b->T, b->d_cases, parity, b->d_t, b->d_active, b->waves_x, b->rows_per_block, st);
     if (e == hipSuccess && with_tick) e = ij::launch_batch_tick(b->d_t, st);
     return e;
 }
@@ -328,16 +347,18 @@ std::vector<int64_t> signature(const ij_batch* b)
     return sig;
 }
 
-ij_status apply_tiling(ij_batch* b, int waves_x, int rows)
+ij_status apply_tiling(ij_batch* b, int waves_x, int rows, int mixed, int persistent)
 {
     for (ij_sim* s : b->sims) {
         s->waves_x = waves_x;
         s->rows_per_block = rows;
-        s->mixed_strips = true;
+        s->mixed_strips = mixed != 0;
         if (build_plain(s) != IJ_OK) return bfail(b, IJ_ERR_DEVICE, s->err);
     }
     b->waves_x = waves_x;
     b->rows_per_block = rows;
+    b->mixed = mixed != 0;
+    b->persistent = persistent != 0;
     return build_tiles(b);
 }
 
@@ -386,7 +407,7 @@ ij_status ij_batch_create(const ij_params* cases, int32_t n, ij_batch** out)
         hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess)
         return cleanup(IJ_ERR_DEVICE, "stream or event creation failed");
-    const ij_status r = apply_tiling(b, b->waves_x, b->rows_per_block);
+    const ij_status r = apply_tiling(b, b->waves_x, b->rows_per_block, b->mixed, b->persistent);
     if (r != IJ_OK) return cleanup(r, b->err);
     *out = b;
     return IJ_OK;
@@ -438,20 +459,24 @@ ij_status ij_batch_set_graph(ij_batch* b, int32_t steps_per_graph)
     return IJ_OK;
 }
 
-ij_status ij_batch_set_tiling(ij_batch* b, int32_t waves_x, int32_t rows_per_block)
+ij_status ij_batch_set_tiling(ij_batch* b, int32_t waves_x, int32_t rows_per_block, int32_t mixed_strips,
+                              int32_t persistent)
 {
     if (!b) return IJ_ERR_INVALID_ARG;
     if (waves_x != 1 && waves_x != 2 && waves_x != 4) return bfail(b, IJ_ERR_INVALID_ARG, "waves_x must be 1, 2 or 4");
     if (rows_per_block < 1 || rows_per_block > 1024)
         return bfail(b, IJ_ERR_INVALID_ARG, "rows_per_block must lie in [1, 1024]");
-    return apply_tiling(b, waves_x, rows_per_block);
+    return apply_tiling(b, waves_x, rows_per_block, mixed_strips != 0, persistent != 0);
 }
 
-ij_status ij_batch_get_tiling(const ij_batch* b, int32_t* waves_x, int32_t* rows_per_block)
+ij_status ij_batch_get_tiling(const ij_batch* b, int32_t* waves_x, int32_t* rows_per_block, int32_t* mixed_strips,
+                              int32_t* persistent)
 {
     if (!b) return IJ_ERR_INVALID_ARG;
     if (waves_x) *waves_x = b->waves_x;
     if (rows_per_block) *rows_per_block = b->rows_per_block;
+    if (mixed_strips) *mixed_strips = b->mixed;
+    if (persistent) *persistent = b->persistent;
     return IJ_OK;
 }
 
@@ -488,7 +513,7 @@ ij_status ij_batch_step(ij_batch* b, int64_t nsteps, void* stream)
 }
 
 ij_status ij_batch_autotune(ij_batch* b, int32_t trial_steps, void* stream, int32_t* waves_x, int32_t* rows_per_block,
-                            double* ms_per_step)
+                            int32_t* mixed_strips, int32_t* persistent, double* ms_per_step)
 {
     if (!b) return IJ_ERR_INVALID_ARG;
     if (trial_steps < 2 || trial_steps > 10000) return bfail(b, IJ_ERR_INVALID_ARG, "trial_steps must lie in [2, 10000]");
@@ -500,10 +525,12 @@ ij_status ij_batch_autotune(ij_batch* b, int32_t trial_steps, void* stream, int3
         std::lock_guard<std::mutex> lk(g_tune_mutex);
         auto it = g_tune_cache.find(sig);
         if (it != g_tune_cache.end()) {
-            r = apply_tiling(b, it->second.first, it->second.second);
+            r = apply_tiling(b, it->second.waves_x, it->second.rows, it->second.mixed, it->second.persistent);
             if (r != IJ_OK) return r;
             if (waves_x) *waves_x = b->waves_x;
             if (rows_per_block) *rows_per_block = b->rows_per_block;
+            if (mixed_strips) *mixed_strips = b->mixed;
+            if (persistent) *persistent = b->persistent;
             if (ms_per_step) *ms_per_step = -1.0;   // from the cache, not timed
             return IJ_OK;
         }
@@ -532,12 +559,14 @@ ij_status ij_batch_autotune(ij_batch* b, int32_t trial_steps, void* stream, int3
         release();
         return bfail(b, IJ_ERR_DEVICE, "event creation failed");
     }
-    const int old_w = b->waves_x, old_r = b->rows_per_block;
+    const int old_w = b->waves_x, old_r = b->rows_per_block, old_m = b->mixed, old_p = b->persistent;
     double best = 1e300;
-    int bw = old_w, br = old_r;
+    int bw = old_w, br = old_r, bm = old_m, bp = old_p;
     trial_steps += trial_steps & 1;   // even: every trial ends on the buffer it started from
-    for (const auto& cand : kCandidates) {
-        r = apply_tiling(b, cand[0], cand[1]);
+    for (int trial = 0; trial < 2 * (int)(sizeof kCandidates / sizeof kCandidates[0]); ++trial) {
+        const int* cand = kCandidates[trial >> 1];
+        const int pers = trial & 1;
+        r = apply_tiling(b, cand[0], cand[1], cand[2], pers);
         if (r == IJ_OK) r = stage(b, st);   // the tables of the new tiling
         if (r != IJ_OK) break;
         // two untimed steps, then the timed ones (no diagnostics: the tile
@@ -559,6 +588,8 @@ ij_status ij_batch_autotune(ij_batch* b, int32_t trial_steps, void* stream, int3
             best = per;
             bw = cand[0];
             br = cand[1];
+            bm = cand[2];
+            bp = pers;
         }
     }
     // restore the state whatever happened
@@ -570,17 +601,19 @@ ij_status ij_batch_autotune(ij_batch* b, int32_t trial_steps, void* stream, int3
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (r != IJ_OK) {
-        (void)apply_tiling(b, old_w, old_r);
+        (void)apply_tiling(b, old_w, old_r, old_m, old_p);
         return r;
     }
-    r = apply_tiling(b, bw, br);
+    r = apply_tiling(b, bw, br, bm, bp);
     if (r != IJ_OK) return r;
     {
         std::lock_guard<std::mutex> lk(g_tune_mutex);
-        g_tune_cache[sig] = {bw, br};
+        g_tune_cache[sig] = {bw, br, bm, bp};
     }
     if (waves_x) *waves_x = bw;
     if (rows_per_block) *rows_per_block = br;
+    if (mixed_strips) *mixed_strips = bm;
+    if (persistent) *persistent = bp;
     if (ms_per_step) *ms_per_step = best;
     return IJ_OK;
 }

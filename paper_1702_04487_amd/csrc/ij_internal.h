@@ -13,7 +13,10 @@ namespace ij_host {
 
 constexpr int kPitchAlign = 64;    // floats: 256-byte rows
 constexpr int64_t kSampleCap = 4096;
-constexpr int kGeneralRows = 4;    // rows per tile of the launch over rows next to solid nodes
+// rows per tile of the launch over rows next to solid nodes: short tiles
+// when such rows are few and scattered (many workgroups, little marching),
+// taller ones when a strip has long runs of them (less pipeline overhead)
+constexpr int kGeneralRowsShort = 4, kGeneralRowsTall = 16, kGeneralTallRun = 32;
 
 inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
@@ -55,6 +58,7 @@ struct ij_sim {
     std::vector<int> gtiles_host;
     int n_strips = 0, n_rb = 0;   // of the plain launch's tiling
     int n_wide = 0;               // strips 64 * waves_x wide; the others are 64 wide
+    int rows_general = ij_host::kGeneralRowsShort;   // rows per general tile
     bool mixed_strips = false;    // tail strips of 64 columns (batches)
     bool in_batch = false;        // owned and stepped by an ij_batch
     std::string err;

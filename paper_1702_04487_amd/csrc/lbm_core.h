@@ -53,6 +53,7 @@ struct CaseRec {
     SampleRec* ring;        // diagnostics records
     int n_ghost, n_strips, row0, a_min;
     int n_wide, wide_w;     // strips 0..n_wide-1 are wide_w columns wide, the others 64
+    int rows_general;       // rows per tile of the general launch
     int64_t t_pos, t_neg, t_idle;
     int periodic;
     double f_pos, f_neg, u_limit;
@@ -80,17 +81,18 @@ hipError_t launch_diag(const KParams& P, const float* A, const uint8_t* wall, co
                        int a_min, int64_t step, DiagRow* rows, SampleRec* out, hipStream_t st);
 
 // (case, strip, row block, -) tiles of a batch: plain tiles (rows_per_block
-// rows) and general tiles (rows_general rows) of the wide strips (workgroups
-// of 64 * waves_x lanes) and of the 64-column tail strips (one wave).  The
-// plain launches are persistent with grid_wide / grid_tail workgroups, each
-// running a contiguous run of tiles.
+// rows) and general tiles (each case's rows_general rows) of the wide strips
+// (workgroups of 64 * waves_x lanes) and of the 64-column tail strips (one
+// wave).  The plain launches run grid_wide / grid_tail workgroups, each over
+// a contiguous run of tiles (a grid of one workgroup per tile when it equals
+// the tile count).
 struct BatchTiles {
     const int4 *wide, *tail, *gwide, *gtail;
     int n_wide, n_tail, n_gwide, n_gtail;
     int grid_wide, grid_tail;
 };
 hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int64_t* t_dev,
-                                const int* active, int waves_x, int rows_per_block, int rows_general, hipStream_t st);
+                                const int* active, int waves_x, int rows_per_block, hipStream_t st);
 hipError_t launch_batch_tick(int64_t* t_dev, hipStream_t st);
 hipError_t launch_batch_set_time(int64_t* t_dev, int64_t t, hipStream_t st);
 hipError_t launch_batch_diag(const CaseRec* cases, int n_cases, int max_nx, int max_ny, int max_ghost, int parity,

@@ -1229,7 +1229,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __rest
         const float fb = (float)case_pulse(R, t);
         const int x0 = tl.y < R.n_wide ? tl.y * R.wide_w : R.n_wide * R.wide_w + (tl.y - R.n_wide) * 64;
         collide_tile<NW, PLAIN>(P, fb, R.buf[parity], R.buf[1 - parity], R.wall, R.plain, tl.y, x0, tl.z,
-                                rows_per_block);
+                                PLAIN ? rows_per_block : R.rows_general);
     }
 }
 
@@ -1354,11 +1354,9 @@ int batch_resident_workgroups(int waves_x)
 }
 
 hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int64_t* t_dev,
-                                const int* active, int waves_x, int rows_per_block, int rows_general, hipStream_t st)
+                                const int* active, int waves_x, int rows_per_block, hipStream_t st)
 {
-    if (rows_per_block < 1 || rows_per_block > kMaxRowsPerBlock || rows_general < 1 ||
-        rows_general > kMaxRowsPerBlock || (parity & ~1))
-        return hipErrorInvalidValue;
+    if (rows_per_block < 1 || rows_per_block > kMaxRowsPerBlock || (parity & ~1)) return hipErrorInvalidValue;
     // persistent plain launches (one per strip width), then the general tiles
     auto persistent = [&](int n, int grid, int& per_wg) {
         grid = n > 0 ? std::min(grid, n) : 0;
@@ -1373,14 +1371,14 @@ hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int p
                            parity, t_dev, active, rows_per_block);
     if (T.n_gtail > 0)
         hipLaunchKernelGGL((k_batch_collide<1, false>), dim3(T.n_gtail), dim3(64), 0, st, cases, T.gtail, T.n_gtail,
-                           1, parity, t_dev, active, rows_general);
+                           1, parity, t_dev, active, 0);
 #define IJ_BLAUNCH(NWV)                                                                                       \
     if (gw > 0)                                                                                               \
         hipLaunchKernelGGL((k_batch_collide<NWV, true>), dim3(gw), dim3(64 * NWV), 0, st, cases, T.wide,       \
                            T.n_wide, pw, parity, t_dev, active, rows_per_block);                              \
     if (T.n_gwide > 0)                                                                                        \
         hipLaunchKernelGGL((k_batch_collide<NWV, false>), dim3(T.n_gwide), dim3(64 * NWV), 0, st, cases, T.gwide, \
-                           T.n_gwide, 1, parity, t_dev, active, rows_general);
+                           T.n_gwide, 1, parity, t_dev, active, 0);
     switch (waves_x) {
     case 1: IJ_BLAUNCH(1) break;
     case 2: IJ_BLAUNCH(2) break;

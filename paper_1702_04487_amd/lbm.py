@@ -106,10 +106,11 @@ def load(path: str = LIB_PATH):
         "ij_batch_time": (i64, [vp]),
         "ij_batch_step": (st, [vp, i64, vp]),
         "ij_batch_set_graph": (st, [vp, i32]),
-        "ij_batch_set_tiling": (st, [vp, i32, i32]),
-        "ij_batch_get_tiling": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
-        "ij_batch_autotune": (st, [vp, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                   ctypes.POINTER(ctypes.c_double)]),
+        "ij_batch_set_tiling": (st, [vp, i32, i32, i32, i32]),
+        "ij_batch_get_tiling": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                     ctypes.POINTER(i32)]),
+        "ij_batch_autotune": (st, [vp, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                   ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
         "ij_mlp_create": (st, [i32, ctypes.POINTER(vp)]),
         "ij_mlp_destroy": (None, [vp]),
         "ij_mlp_last_error": (ctypes.c_char_p, [vp]),
@@ -367,20 +368,24 @@ class Batch:
     def set_graph(self, steps_per_graph: int):
         self._check(self.L.ij_batch_set_graph(self.h, int(steps_per_graph)))
 
-    def set_tiling(self, waves_x: int, rows_per_block: int):
-        self._check(self.L.ij_batch_set_tiling(self.h, int(waves_x), int(rows_per_block)))
+    def set_tiling(self, waves_x: int, rows_per_block: int, mixed_strips: bool = False, persistent: bool = True):
+        self._check(self.L.ij_batch_set_tiling(self.h, int(waves_x), int(rows_per_block), int(bool(mixed_strips)),
+                                               int(bool(persistent))))
 
     def tiling(self):
-        w, r = ctypes.c_int32(0), ctypes.c_int32(0)
-        self._check(self.L.ij_batch_get_tiling(self.h, ctypes.byref(w), ctypes.byref(r)))
-        return int(w.value), int(r.value)
+        """(waves_x, rows_per_block, mixed_strips, persistent)."""
+        w, r, m, p = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        self._check(self.L.ij_batch_get_tiling(self.h, ctypes.byref(w), ctypes.byref(r), ctypes.byref(m),
+                                               ctypes.byref(p)))
+        return int(w.value), int(r.value), bool(m.value), bool(p.value)
 
     def autotune(self, trial_steps: int = 20, stream=None):
-        """Returns (waves_x, rows_per_block, ms per step or -1 if cached)."""
-        w, r, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+        """Returns (waves_x, rows_per_block, mixed_strips, persistent, ms per
+        step or -1 if cached)."""
+        w, r, m, p, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
         self._check(self.L.ij_batch_autotune(self.h, int(trial_steps), _stream_ptr(stream), ctypes.byref(w),
-                                             ctypes.byref(r), ctypes.byref(ms)))
-        return int(w.value), int(r.value), float(ms.value)
+                                             ctypes.byref(r), ctypes.byref(m), ctypes.byref(p), ctypes.byref(ms)))
+        return int(w.value), int(r.value), bool(m.value), bool(p.value), float(ms.value)
 
 
 MLP_NAMES = ("W1", "b1", "W2", "b2", "W3", "b3")

@@ -134,8 +134,8 @@ def test_batch_autotune_keeps_state_and_caches(gpu_lib):
     b = _batch(L, cases)
     b.step(20)
     before = [c.state() for c in b.cases]
-    w, r, ms = b.autotune(6)
-    assert (w, r) == b.tiling() and w in (1, 2, 4) and r in (16, 32, 64) and ms > 0
+    w, r, m, per, ms = b.autotune(6)
+    assert (w, r, m, per) == b.tiling() and w in (1, 2, 4) and r in (16, 32, 64) and ms > 0
     for c, (f0, g0) in zip(b.cases, before):
         f1, g1 = c.state()
         assert bool((f0 == f1).all() and (g0 == g1).all())
@@ -145,8 +145,8 @@ def test_batch_autotune_keeps_state_and_caches(gpu_lib):
     for bc, sc in zip(b.cases, singles):
         assert _same(bc, sc) and _same_samples(bc, sc)
     b2 = _batch(L, cases)
-    w2, r2, ms2 = b2.autotune(6)
-    assert (w2, r2) == (w, r) and ms2 == -1.0   # same shapes: from the cache
+    w2, r2, m2, p2, ms2 = b2.autotune(6)
+    assert (w2, r2, m2, p2) == (w, r, m, per) and ms2 == -1.0   # same shapes: from the cache
     b.close()
     b2.close()
 
@@ -155,13 +155,14 @@ def test_batch_tile_shapes_are_bitwise_equal(gpu_lib):
     L = gpu_lib
     cases = _cases()
     runs = []
-    for shape in [(1, 16), (2, 7), (4, 64)]:
+    for shape in [(1, 16, False, True), (2, 7, True, False), (4, 64, False, False), (4, 32, True, True)]:
         b = _batch(L, cases)
         b.set_tiling(*shape)
         b.set_graph(10)
         b.step(50)
         runs.append(b)
     for i in range(len(cases)):
-        assert _same(runs[0].cases[i], runs[1].cases[i]) and _same(runs[0].cases[i], runs[2].cases[i]), i
+        for other in runs[1:]:
+            assert _same(runs[0].cases[i], other.cases[i]), i
     for b in runs:
         b.close()
