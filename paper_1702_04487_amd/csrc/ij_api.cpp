@@ -211,7 +211,6 @@ ij_status build_plain(ij_sim* s)
     const bool open = s->p.bc_y == IJ_BC_OPEN;
     // rows with any solid node in a column window: per strip
     std::vector<uint8_t> plain((size_t)n_strips * ny, 0);
-    std::vector<int> tiles;
     for (int k = 0; k < n_strips; ++k) {
         const int x0 = strip_x0(k), w = strip_w(k);
         std::vector<uint8_t> solid_row(ny, 0);
@@ -244,32 +243,42 @@ ij_status build_plain(ij_sim* s)
     const int kGeneralRows = s->in_batch && longest >= kGeneralTallRun ? kGeneralRowsTall : kGeneralRowsShort;
     s->rows_general = kGeneralRows;
     const int n_rb_g = (ny + kGeneralRows - 1) / kGeneralRows;
+    // general tiles: 64-column pieces (one wave each) of the (strip, block)
+    // pairs that hold a non-plain row; a piece without a fluid node in the
+    // block's rows has nothing to collide and is left out
+    std::vector<int4> gt;   // (strip, block, first column, 0)
     for (int b = 0; b < n_rb_g; ++b)
         for (int k = 0; k < n_strips; ++k) {
             const int y0 = b * kGeneralRows, y1 = std::min(ny, y0 + kGeneralRows);
             bool general = false;
             for (int y = y0; y < y1 && !general; ++y) general = !plain[(size_t)k * ny + y];
-            if (general) tiles.push_back(b * n_strips + k);
+            if (!general) continue;
+            const int sx0 = strip_x0(k), sx1 = sx0 + strip_w(k);
+            for (int c0 = sx0; c0 < sx1; c0 += 64) {
+                const int c1 = std::min(sx1, c0 + 64);
+                bool fluid = false;
+                for (int y = y0; y < y1 && !fluid; ++y)
+                    for (int x = c0; x < c1 && !fluid; ++x) fluid = s->wall_host[(size_t)y * nx + x] == 0;
+                if (fluid) gt.push_back(make_int4(k, b, c0, 0));
+            }
         }
     s->n_strips = n_strips;
     s->n_wide = n_wide;
     s->n_rb = (ny + s->rows_per_block - 1) / s->rows_per_block;
-    s->gtiles_host = tiles;
-    s->n_strips = n_strips;
-    s->n_wide = n_wide;
-    s->n_rb = (ny + s->rows_per_block - 1) / s->rows_per_block;
-    s->gtiles_host = tiles;
+    s->strip_x0.resize((size_t)n_strips);
+    for (int k = 0; k < n_strips; ++k) s->strip_x0[(size_t)k] = strip_x0(k);
+    s->gtiles_host = gt;
     if (s->plain) (void)hipFree(s->plain);
     if (s->gtiles) (void)hipFree(s->gtiles);
     s->plain = nullptr;
     s->gtiles = nullptr;
     if (hipMalloc(&s->plain, plain.size()) != hipSuccess) return fail(s, IJ_ERR_OOM, "plain-row table allocation failed");
     IJ_HIP(s, hipMemcpy(s->plain, plain.data(), plain.size(), hipMemcpyHostToDevice));
-    s->n_gtiles = (int)tiles.size();
+    s->n_gtiles = (int)gt.size();
     if (s->n_gtiles) {
-        if (hipMalloc(&s->gtiles, tiles.size() * sizeof(int)) != hipSuccess)
+        if (hipMalloc(&s->gtiles, gt.size() * sizeof(int4)) != hipSuccess)
             return fail(s, IJ_ERR_OOM, "tile list allocation failed");
-        IJ_HIP(s, hipMemcpy(s->gtiles, tiles.data(), tiles.size() * sizeof(int), hipMemcpyHostToDevice));
+        IJ_HIP(s, hipMemcpy(s->gtiles, gt.data(), gt.size() * sizeof(int4), hipMemcpyHostToDevice));
     }
     return IJ_OK;
 }

@@ -137,15 +137,13 @@ ij_status set_grids(ij_batch* b)
 // tile lists of the launches from the members' current tilings
 ij_status build_tiles(ij_batch* b)
 {
-    std::vector<int4> lists[4];   // wide, tail, general wide, general tail
+    std::vector<int4> lists[3];   // wide, tail, general
     for (size_t c = 0; c < b->sims.size(); ++c) {
         const ij_sim* s = b->sims[c];
         for (int rb = 0; rb < s->n_rb; ++rb)
-            for (int k = 0; k < s->n_strips; ++k) lists[k < s->n_wide ? 0 : 1].push_back(make_int4((int)c, k, rb, 0));
-        for (int g : s->gtiles_host) {
-            const int k = g % s->n_strips, rb = g / s->n_strips;
-            lists[k < s->n_wide ? 2 : 3].push_back(make_int4((int)c, k, rb, 0));
-        }
+            for (int k = 0; k < s->n_strips; ++k)
+                lists[k < s->n_wide ? 0 : 1].push_back(make_int4((int)c, k, rb, s->strip_x0[(size_t)k]));
+        for (const int4& g : s->gtiles_host) lists[2].push_back(make_int4((int)c, g.x, g.y, g.z));
     }
     int mg = 0;
     for (const ij_sim* s : b->sims) mg = std::max(mg, s->n_ghost);
@@ -155,11 +153,10 @@ ij_status build_tiles(ij_batch* b)
     }
     std::vector<int4> all;
     for (auto& l : lists) all.insert(all.end(), l.begin(), l.end());
-    const int counts[4] = {(int)lists[0].size(), (int)lists[1].size(), (int)lists[2].size(), (int)lists[3].size()};
+    const int counts[3] = {(int)lists[0].size(), (int)lists[1].size(), (int)lists[2].size()};
     const bool same = all.size() == b->tiles_host.size() &&
                       std::memcmp(all.data(), b->tiles_host.data(), all.size() * sizeof(int4)) == 0 &&
-                      counts[0] == b->T.n_wide && counts[1] == b->T.n_tail && counts[2] == b->T.n_gwide &&
-                      counts[3] == b->T.n_gtail;
+                      counts[0] == b->T.n_wide && counts[1] == b->T.n_tail && counts[2] == b->T.n_gen;
     if (same && (b->d_tiles || all.empty())) return set_grids(b);
     if (all.size() > b->cap_tiles) {
         if (b->d_tiles) (void)hipFree(b->d_tiles);
@@ -174,12 +171,10 @@ ij_status build_tiles(ij_batch* b)
     ij::BatchTiles& T = b->T;
     T.wide = b->d_tiles;
     T.tail = T.wide + counts[0];
-    T.gwide = T.tail + counts[1];
-    T.gtail = T.gwide + counts[2];
+    T.gen = T.tail + counts[1];
     T.n_wide = counts[0];
     T.n_tail = counts[1];
-    T.n_gwide = counts[2];
-    T.n_gtail = counts[3];
+    T.n_gen = counts[2];
     drop_graph(b);
     return set_grids(b);
 }
@@ -203,9 +198,6 @@ ij_status stage(ij_batch* b, hipStream_t st)
         r.rows = s->rows;
         r.ring = s->samples;
         r.n_ghost = s->n_ghost;
-        r.n_strips = s->n_strips;
-        r.n_wide = s->n_wide;
-        r.wide_w = 64 * s->waves_x;
         r.rows_general = s->rows_general;
         r.row0 = (int)s->p.diag_row0;
         r.a_min = (int)std::ceil(4.0 * s->p.width * s->p.width);

@@ -53,9 +53,10 @@ struct ij_sim {
     // rows of each strip the plain collide-stream path may take, and the
     // tiles that hold the other rows (rebuilt with the wall or the tiling)
     uint8_t* plain = nullptr;
-    int* gtiles = nullptr;
+    int4* gtiles = nullptr;            // (strip, block, first column, 0) of the general launch
     int n_gtiles = 0;
-    std::vector<int> gtiles_host;
+    std::vector<int4> gtiles_host;
+    std::vector<int> strip_x0;         // first column of each strip
     int n_strips = 0, n_rb = 0;   // of the plain launch's tiling
     int n_wide = 0;               // strips 64 * waves_x wide; the others are 64 wide
     int rows_general = ij_host::kGeneralRowsShort;   // rows per general tile

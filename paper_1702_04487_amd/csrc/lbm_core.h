@@ -51,8 +51,7 @@ struct CaseRec {
     const int2* ghost;      // solid nodes that touch fluid
     DiagRow* rows;          // [ny]
     SampleRec* ring;        // diagnostics records
-    int n_ghost, n_strips, row0, a_min;
-    int n_wide, wide_w;     // strips 0..n_wide-1 are wide_w columns wide, the others 64
+    int n_ghost, row0, a_min;
     int rows_general;       // rows per tile of the general launch
     int64_t t_pos, t_neg, t_idle;
     int periodic;
@@ -65,10 +64,11 @@ hipError_t launch_collide_ref(const KParams& P, const float* A, float* B, const 
                               const double* phi, hipStream_t st);
 // plain_rows: [n_strips][ny] bytes, 1 where the row of the strip is plain
 // (see the kernel).  The plain launch covers every tile of rows_per_block
-// rows; general_tiles lists the tiles of rows_general rows (numbered
-// block * n_strips + strip) that hold other rows.
+// rows of the strips of 64 * waves_x columns; general_tiles lists the
+// (strip, block of rows_general rows, first column, -) pieces, 64 columns
+// wide, that hold other rows.
 hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, const uint8_t* wall,
-                                const uint8_t* plain_rows, const int* general_tiles, int n_general_tiles,
+                                const uint8_t* plain_rows, const int4* general_tiles, int n_general_tiles,
                                 int waves_x, int rows_per_block, int rows_general, hipStream_t st);
 hipError_t launch_init(const KParams& P, float* A, const uint8_t* wall, double* phi, const float* src,
                        int from_distance, const float* ux, const float* uy, const int2* ghost_list,
@@ -80,15 +80,15 @@ hipError_t launch_state_io(const KParams& P, float* A, const uint8_t* wall, floa
 hipError_t launch_diag(const KParams& P, const float* A, const uint8_t* wall, const double* phi, int row0,
                        int a_min, int64_t step, DiagRow* rows, SampleRec* out, hipStream_t st);
 
-// (case, strip, row block, -) tiles of a batch: plain tiles (rows_per_block
-// rows) and general tiles (each case's rows_general rows) of the wide strips
-// (workgroups of 64 * waves_x lanes) and of the 64-column tail strips (one
-// wave).  The plain launches run grid_wide / grid_tail workgroups, each over
-// a contiguous run of tiles (a grid of one workgroup per tile when it equals
-// the tile count).
+// (case, strip, row block, first column) tiles of a batch: plain tiles
+// (rows_per_block rows) of the wide strips (workgroups of 64 * waves_x
+// lanes) and of the 64-column tail strips (one wave), and the 64-column
+// general pieces (one wave, each case's rows_general rows).  The plain
+// launches run grid_wide / grid_tail workgroups, each over a contiguous run
+// of tiles (a grid of one workgroup per tile when it equals the tile count).
 struct BatchTiles {
-    const int4 *wide, *tail, *gwide, *gtail;
-    int n_wide, n_tail, n_gwide, n_gtail;
+    const int4 *wide, *tail, *gen;
+    int n_wide, n_tail, n_gen;
     int grid_wide, grid_tail;
 };
 hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int64_t* t_dev,

@@ -814,27 +814,27 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
 // One lattice: the PLAIN launch covers every tile, numbered row-block major
 // and dealt so that runs of consecutive tiles stay on one XCD (workgroups are
 // dealt round-robin over the 8 XCDs, each with its own L2); the other launch
-// takes the tiles of tile_list.
+// takes the (strip, block, first column) pieces of tile_list.
 template <int NW, bool PLAIN>
 __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const float* __restrict__ A,
                                                            float* __restrict__ B,
                                                            const uint8_t* __restrict__ wall,
                                                            const uint8_t* __restrict__ plain_rows,
-                                                           const int* __restrict__ tile_list,
+                                                           const int4* __restrict__ tile_list,
                                                            int rows_per_block, int n_strips,
                                                            int n_rowblocks)
 {
-    int tile;
     if (PLAIN) {
         const int ntiles = n_strips * n_rowblocks;
-        tile = blockIdx.x;
+        int tile = blockIdx.x;
         if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
+        const int rb = tile / n_strips;
+        const int strip = tile - rb * n_strips;
+        collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, strip, strip * 64 * NW, rb, rows_per_block);
     } else {
-        tile = tile_list[blockIdx.x];
+        const int4 tl = tile_list[blockIdx.x];
+        collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, tl.x, tl.z, tl.y, rows_per_block);
     }
-    const int rb = tile / n_strips;
-    const int strip = tile - rb * n_strips;
-    collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, strip, strip * 64 * NW, rb, rows_per_block);
 }
 
 // ------------------------------------------------------------ init / moments
@@ -1208,11 +1208,10 @@ __device__ __forceinline__ double case_pulse(const CaseRec& c, int64_t t)
     return 0.0;
 }
 
-// Persistent over tiles: workgroup b runs tiles [b * per_wg, (b + 1) *
-// per_wg) of the (case, strip, row block) list, in order (neighbouring tiles
-// of a case share their halo rows through the cache).  A case's strips are
-// R.n_wide strips of R.wide_w columns, then 64-column strips; a launch takes
-// the tiles of its own strip width (64 * NW).
+// Workgroup b runs tiles [b * per_wg, (b + 1) * per_wg) of the (case,
+// strip, row block, first column) list, in order (neighbouring tiles of a
+// case share their halo rows through the cache); a launch takes the tiles
+// of its own width (64 * NW columns).
 template <int NW, bool PLAIN>
 __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __restrict__ cases,
                                                            const int4* __restrict__ tiles, int n_tiles,
@@ -1222,13 +1221,12 @@ __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __rest
     const int64_t t = *t_dev;
     const int i0 = blockIdx.x * per_wg, i1 = min(n_tiles, i0 + per_wg);
     for (int i = i0; i < i1; ++i) {
-        const int4 tl = tiles[i];   // (case, strip, row block, -)
+        const int4 tl = tiles[i];   // (case, strip, row block, first column)
         if (!active[tl.x]) continue;
         const CaseRec& R = cases[tl.x];
         const KParams P = R.P;
         const float fb = (float)case_pulse(R, t);
-        const int x0 = tl.y < R.n_wide ? tl.y * R.wide_w : R.n_wide * R.wide_w + (tl.y - R.n_wide) * 64;
-        collide_tile<NW, PLAIN>(P, fb, R.buf[parity], R.buf[1 - parity], R.wall, R.plain, tl.y, x0, tl.z,
+        collide_tile<NW, PLAIN>(P, fb, R.buf[parity], R.buf[1 - parity], R.wall, R.plain, tl.y, tl.w, tl.z,
                                 PLAIN ? rows_per_block : R.rows_general);
     }
 }
@@ -1310,7 +1308,7 @@ hipError_t launch_collide_ref(const KParams& P, const float* A, float* B, const 
 }
 
 hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, const uint8_t* wall,
-                                const uint8_t* plain_rows, const int* general_tiles, int n_general_tiles,
+                                const uint8_t* plain_rows, const int4* general_tiles, int n_general_tiles,
                                 int waves_x, int rows_per_block, int rows_general, hipStream_t st)
 {
     if (rows_per_block < 1 || rows_per_block > kMaxRowsPerBlock || rows_general < 1 ||
@@ -1319,22 +1317,27 @@ hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, cons
     const int bw = 64 * waves_x;
     const int n_strips = (P.nx + bw - 1) / bw;
     const int n_rb = (P.ny + rows_per_block - 1) / rows_per_block;
-    const int n_rb_g = (P.ny + rows_general - 1) / rows_general;
-    const dim3 grid(n_strips * n_rb), ggrid(n_general_tiles);
-#define IJ_LAUNCH(NWV)                                                                                      \
-    hipLaunchKernelGGL((k_collide_fused<NWV, true>), grid, dim3(64 * NWV), 0, st, P, A, B, wall, plain_rows,  \
-                       general_tiles, rows_per_block, n_strips, n_rb);                                      \
-    if (n_general_tiles > 0)                                                                                \
-        hipLaunchKernelGGL((k_collide_fused<NWV, false>), ggrid, dim3(64 * NWV), 0, st, P, A, B, wall,       \
-                           plain_rows, general_tiles, rows_general, n_strips, n_rb_g);
+    const dim3 grid(n_strips * n_rb);
     switch (waves_x) {
-    case 1: IJ_LAUNCH(1) break;
-    case 2: IJ_LAUNCH(2) break;
-    case 4: IJ_LAUNCH(4) break;
+    case 1:
+        hipLaunchKernelGGL((k_collide_fused<1, true>), grid, dim3(64), 0, st, P, A, B, wall, plain_rows,
+                           general_tiles, rows_per_block, n_strips, n_rb);
+        break;
+    case 2:
+        hipLaunchKernelGGL((k_collide_fused<2, true>), grid, dim3(128), 0, st, P, A, B, wall, plain_rows,
+                           general_tiles, rows_per_block, n_strips, n_rb);
+        break;
+    case 4:
+        hipLaunchKernelGGL((k_collide_fused<4, true>), grid, dim3(256), 0, st, P, A, B, wall, plain_rows,
+                           general_tiles, rows_per_block, n_strips, n_rb);
+        break;
     default:
         return hipErrorInvalidValue;
     }
-#undef IJ_LAUNCH
+    // the general pieces are 64 columns wide: one wave each
+    if (n_general_tiles > 0)
+        hipLaunchKernelGGL((k_collide_fused<1, false>), dim3(n_general_tiles), dim3(64), 0, st, P, A, B, wall,
+                           plain_rows, general_tiles, rows_general, n_strips, n_rb);
     return hipGetLastError();
 }
 
@@ -1357,36 +1360,40 @@ hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int p
                                 const int* active, int waves_x, int rows_per_block, hipStream_t st)
 {
     if (rows_per_block < 1 || rows_per_block > kMaxRowsPerBlock || (parity & ~1)) return hipErrorInvalidValue;
-    // persistent plain launches (one per strip width), then the general tiles
-    auto persistent = [&](int n, int grid, int& per_wg) {
+    // plain launches (one per strip width; persistent when the grid is
+    // smaller than the tile count), then the general pieces
+    auto runs = [&](int n, int grid, int& per_wg) {
         grid = n > 0 ? std::min(grid, n) : 0;
         per_wg = grid > 0 ? (n + grid - 1) / grid : 0;
         return per_wg > 0 ? (n + per_wg - 1) / per_wg : 0;
     };
     int pw = 0, pt = 0;
-    const int gw = persistent(T.n_wide, T.grid_wide, pw);
-    const int gt = persistent(T.n_tail, T.grid_tail, pt);
+    const int gw = runs(T.n_wide, T.grid_wide, pw);
+    const int gt = runs(T.n_tail, T.grid_tail, pt);
     if (gt > 0)
         hipLaunchKernelGGL((k_batch_collide<1, true>), dim3(gt), dim3(64), 0, st, cases, T.tail, T.n_tail, pt,
                            parity, t_dev, active, rows_per_block);
-    if (T.n_gtail > 0)
-        hipLaunchKernelGGL((k_batch_collide<1, false>), dim3(T.n_gtail), dim3(64), 0, st, cases, T.gtail, T.n_gtail,
-                           1, parity, t_dev, active, 0);
-#define IJ_BLAUNCH(NWV)                                                                                       \
-    if (gw > 0)                                                                                               \
-        hipLaunchKernelGGL((k_batch_collide<NWV, true>), dim3(gw), dim3(64 * NWV), 0, st, cases, T.wide,       \
-                           T.n_wide, pw, parity, t_dev, active, rows_per_block);                              \
-    if (T.n_gwide > 0)                                                                                        \
-        hipLaunchKernelGGL((k_batch_collide<NWV, false>), dim3(T.n_gwide), dim3(64 * NWV), 0, st, cases, T.gwide, \
-                           T.n_gwide, 1, parity, t_dev, active, 0);
-    switch (waves_x) {
-    case 1: IJ_BLAUNCH(1) break;
-    case 2: IJ_BLAUNCH(2) break;
-    case 4: IJ_BLAUNCH(4) break;
-    default:
-        return hipErrorInvalidValue;
+    if (gw > 0) {
+        switch (waves_x) {
+        case 1:
+            hipLaunchKernelGGL((k_batch_collide<1, true>), dim3(gw), dim3(64), 0, st, cases, T.wide, T.n_wide, pw,
+                               parity, t_dev, active, rows_per_block);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_batch_collide<2, true>), dim3(gw), dim3(128), 0, st, cases, T.wide, T.n_wide, pw,
+                               parity, t_dev, active, rows_per_block);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_batch_collide<4, true>), dim3(gw), dim3(256), 0, st, cases, T.wide, T.n_wide, pw,
+                               parity, t_dev, active, rows_per_block);
+            break;
+        default:
+            return hipErrorInvalidValue;
+        }
     }
-#undef IJ_BLAUNCH
+    if (T.n_gen > 0)
+        hipLaunchKernelGGL((k_batch_collide<1, false>), dim3(T.n_gen), dim3(64), 0, st, cases, T.gen, T.n_gen, 1,
+                           parity, t_dev, active, 0);
     return hipGetLastError();
 }
 

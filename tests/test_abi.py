@@ -39,7 +39,9 @@ def test_invalid_parameters_are_rejected_without_a_device():
     bad_cases = [dict(good, nx=2), dict(good, tau_ink=0.5), dict(good, rho_amb=2.0),
                  dict(good, width=0.0), dict(good, theta_inner=181.0), dict(good, bc_y=7),
                  dict(good, t_neg=-1), dict(good, nozzle_w=70, nozzle_x0=1, nozzle_len=10),
-                 dict(good, nx=60000, ny=60000)]
+                 dict(good, nx=60000, ny=60000),
+                 dict(good, nx=64, ny=65536),            # rows beyond the 16-bit limit
+                 dict(good, nx=2240, ny=65535)]          # 15 * ny * pitch >= 2^31
     for bad in bad_cases:
         p = lbm.to_params(bad)
         h = ctypes.c_void_p()
@@ -85,3 +87,12 @@ def test_batch_rejects_invalid_cases_without_a_device():
     assert L.ij_batch_create(None, 0, ctypes.byref(h)) == lbm.IJ_ERR_INVALID_ARG
     L.ij_batch_destroy(None)
     assert L.ij_batch_size(None) == -1 and L.ij_batch_time(None) == -1
+
+
+def test_largest_lattice_is_accepted():
+    from paper_1702_04487_amd import lbm
+    L = lbm.load()
+    p = lbm.to_params(W.base_params(2048, 65535, bc_y=W.BC_PERIODIC))
+    n = ctypes.c_size_t(0)
+    assert L.ij_required_bytes(ctypes.byref(p), ctypes.byref(n)) == lbm.IJ_OK
+    assert n.value == 65535 * 2048 * (14 * 4 + 2)

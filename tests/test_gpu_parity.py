@@ -313,3 +313,32 @@ def test_full_size_single_nozzle_sampled(oracle_mod, gpu_lib):
         errs = _window_compare(oracle_mod, p, wall, d, gm, y0, 0, 64, p["nx"], k, W.BC_OPEN)
         assert errs["n"] < 2e-6 and errs["phi"] < 2e-6, (y0, errs)
         assert errs["ux"] < 1e-7 and errs["uy"] < 1e-7, (y0, errs)
+
+
+def test_largest_accepted_lattice_sampled(oracle_mod, gpu_lib):
+    """The largest lattice the library accepts (ny = 65535, 15 * ny * pitch
+    just under 2^31 with nx = 2048): 32-bit row offsets at their limit.
+    Windows at the first and last rows agree with the oracle after k steps;
+    zero steps is a no-op."""
+    nx, ny = 2048, 65535
+    p = W.base_params(nx, ny, bc_y=W.BC_PERIODIC, force_rows=ny, tau_ink=0.8, theta_inner=120.0,
+                      theta_outer=120.0)
+    wall = W.flat_wall(nx, ny, (0, 1))
+    # a periodic lattice of discs (radius 40 every 128 nodes, shifted per row of discs)
+    y = np.arange(ny, dtype=np.float64)[:, None]
+    x = np.arange(nx, dtype=np.float64)[None, :]
+    cy = np.floor(y / 128.0) * 128.0 + 64.0
+    cx = np.floor((x + 37.0 * np.floor(y / 128.0)) / 128.0) * 128.0 + 64.0 - 37.0 * np.floor(y / 128.0)
+    d = 40.0 - np.sqrt((x - cx) ** 2 + (y - cy) ** 2)
+    d[:4] = -50.0
+    g = gpu_lib.Sim(p, wall)
+    g.init_distance(d)
+    g.step(0)
+    assert g.t == 0
+    k = 4
+    g.step(k)
+    gm = {key: _np(v) for key, v in g.moments().items()}
+    for (y0, x0) in [(0, 200), (ny - 72, 1800), (ny - 40, 1000), (32768, 64)]:
+        errs = _window_compare(oracle_mod, p, wall, d, gm, y0 - 16, x0 - 16, 72, 72, k, W.BC_PERIODIC)
+        assert errs["n"] < 2e-6 and errs["phi"] < 2e-6, (y0, errs)
+        assert errs["ux"] < 1e-7 and errs["uy"] < 1e-7, (y0, errs)
