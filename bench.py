@@ -41,9 +41,9 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1702_04487_amd", "csrc", "lbm_core.hip
 # (2.000 for FETCH_SIZE, 1.000 for WRITE_SIZE).  The figure holds for the
 # kernel source with this SHA-256 only; for any other it is reported as null.
 MEASURED_TRAFFIC = {
-    "kernel_source_sha256": "577257459e70815a1d854f837818921621bb26c31e19ad4508d5876520e52c09",
-    "read_bytes": 2118334563,
-    "write_bytes": 1978625979,
+    "kernel_source_sha256": "1e205e650738597ffa76bdf63a167e1f8fd8d90afcb9cec218d3eb5e5868dd76",
+    "read_bytes": 2120063605,
+    "write_bytes": 1978686433,
 }
 COPY_CEILING_GBS = 5148.4  # best read+write rate of copy_calib on MI355X (float4, 65536 x 256)
 
@@ -57,7 +57,7 @@ def measured_traffic():
     return MEASURED_TRAFFIC["read_bytes"] + MEASURED_TRAFFIC["write_bytes"]
 
 
-def cpu_baseline(cfg, rows: int = 4096, steps: int = 20) -> dict:
+def cpu_baseline(cfg, rows: int = 8192, steps: int = 100) -> dict:
     """FP64 oracle on a full-width band of the same disc field (rows
     [0, rows), periodic), timed over `steps` steps after one warm-up step."""
     from oracle import oracle as O
@@ -89,7 +89,8 @@ def sweep_bench(batched_steps: int = 600, plain_steps: int = 300, plain_every: i
     variant), 40000 steps per case, diagnostics every 50 steps: every case in
     one batch (autotuned tile shape, graphs of 50 steps) timed over
     `batched_steps` steps, against the same cases run one at a time through
-    ij_step (every `plain_every`-th case timed over `plain_steps` steps)."""
+    ij_step, each with its own autotuned tile shape (every `plain_every`-th
+    case timed over `plain_steps` steps)."""
     import torch
     import workloads as W
     from paper_1702_04487_amd import lbm
@@ -126,6 +127,7 @@ def sweep_bench(batched_steps: int = 600, plain_steps: int = 300, plain_every: i
     for c in cases[::plain_every]:
         sim = lbm.Sim(c["params"])
         sim.init_default()
+        sim.autotune(10)   # each case with its own best tile shape
         sim.step(50)
         per_case.append(timed(lambda: sim.step(plain_steps)) / plain_steps)
         sim.close()

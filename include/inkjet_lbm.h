@@ -206,6 +206,13 @@ ij_status ij_check(ij_sim *s, void *stream);
  * wetting offsets 2 Omega phi_star / W, mobility Gamma q (q tau_phi - 1/2). */
 ij_status ij_derived(const ij_sim *s, double out[8]);
 
+/* Autotuner: time trial_steps (2..10000) fused steps for each candidate
+ * tile shape (1, 2, 4 waves x 8, 16, 32, 64 rows), keep the fastest, and
+ * restore the distributions (the step counter does not move).  Outputs may
+ * be NULL.  Synchronises the stream. */
+ij_status ij_autotune(ij_sim *s, int32_t trial_steps, void *stream, int32_t *waves_x, int32_t *rows_per_block,
+                      double *ms_per_step);
+
 /* Tile shape of the fused collide-stream kernel: waves across x per
  * workgroup (1, 2 or 4) and rows per workgroup (1..1024); the default is
  * 4 waves (256 columns) by 32 rows.  0 keeps the current value.  Results

@@ -682,6 +682,75 @@ ij_status ij_derived(const ij_sim* s, double out[8])
     return IJ_OK;
 }
 
+ij_status ij_autotune(ij_sim* s, int32_t trial_steps, void* stream, int32_t* waves_x, int32_t* rows_per_block,
+                      double* ms_per_step)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (s->in_batch) return fail(s, IJ_ERR_STATE, "a batch member takes the batch's tiling (ij_batch_autotune)");
+    if (!s->initialised) return fail(s, IJ_ERR_STATE, "autotune before init");
+    if (trial_steps < 2 || trial_steps > 10000) return fail(s, IJ_ERR_INVALID_ARG, "trial_steps must lie in [2, 10000]");
+    hipStream_t st = (hipStream_t)stream;
+    static const int cand[][2] = {{1, 8}, {1, 16}, {1, 32}, {2, 8}, {2, 16}, {2, 32}, {4, 8}, {4, 16}, {4, 32}, {4, 64}};
+    // trial steps run on the live buffers from a snapshot that is restored
+    const size_t bytes = buffer_bytes(s->plane);
+    void* saved = nullptr;
+    if (hipMalloc(&saved, bytes) != hipSuccess) return fail(s, IJ_ERR_OOM, "autotune snapshot allocation failed");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipMemcpyAsync(saved, s->buf[s->cur], bytes, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const int old_w = s->waves_x, old_r = s->rows_per_block;
+    int bw = old_w, br = old_r;
+    double best = 1e300;
+    trial_steps += trial_steps & 1;
+    s->K.fb = (float)pulse_value(s->p, s->t);
+    for (const auto& c : cand) {
+        if (e != hipSuccess) break;
+        s->waves_x = c[0];
+        s->rows_per_block = c[1];
+        if (build_plain(s) != IJ_OK) {
+            e = hipErrorUnknown;
+            break;
+        }
+        int cur = s->cur;
+        auto steps = [&](int n) {
+            hipError_t r = hipSuccess;
+            for (int k = 0; k < n && r == hipSuccess; ++k) {
+                r = ij::launch_collide_fused(s->K, s->buf[cur], s->buf[1 - cur], s->wall, s->plain, s->gtiles,
+                                             s->n_gtiles, s->waves_x, s->rows_per_block, s->rows_general, st);
+                cur = 1 - cur;
+            }
+            return r;
+        };
+        e = steps(2);
+        if (e == hipSuccess) e = hipEventRecord(e0, st);
+        if (e == hipSuccess) e = steps(trial_steps);
+        if (e == hipSuccess) e = hipEventRecord(e1, st);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e == hipSuccess && ms / trial_steps < best) {
+            best = ms / trial_steps;
+            bw = c[0];
+            br = c[1];
+        }
+    }
+    (void)hipMemcpyAsync(s->buf[s->cur], saved, bytes, hipMemcpyDeviceToDevice, st);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(saved);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    s->waves_x = e == hipSuccess ? bw : old_w;
+    s->rows_per_block = e == hipSuccess ? br : old_r;
+    const ij_status r = build_plain(s);
+    if (e != hipSuccess) return hip_fail(s, e, "autotune trial");
+    if (r != IJ_OK) return r;
+    if (waves_x) *waves_x = bw;
+    if (rows_per_block) *rows_per_block = br;
+    if (ms_per_step) *ms_per_step = best;
+    return IJ_OK;
+}
+
 ij_status ij_set_tiling(ij_sim* s, int32_t waves_x, int32_t rows_per_block)
 {
     if (!s) return IJ_ERR_INVALID_ARG;

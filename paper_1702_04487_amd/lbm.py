@@ -57,7 +57,7 @@ EXPORTS = ["ij_params_default", "ij_create", "ij_destroy", "ij_last_error", "ij_
            "ij_attach_buffers", "ij_set_wall", "ij_init_distance", "ij_init_phi", "ij_init_default",
            "ij_step", "ij_step_reference", "ij_time", "ij_get_moments", "ij_get_state", "ij_set_state",
            "ij_diag_sample", "ij_get_row_profile", "ij_get_samples", "ij_get_diagnostics", "ij_check",
-           "ij_derived", "ij_set_tiling",
+           "ij_derived", "ij_set_tiling", "ij_autotune",
            "ij_batch_create", "ij_batch_destroy", "ij_batch_last_error", "ij_batch_size", "ij_batch_case",
            "ij_batch_time", "ij_batch_step", "ij_batch_set_graph", "ij_batch_set_tiling", "ij_batch_get_tiling",
            "ij_batch_autotune",
@@ -98,6 +98,7 @@ def load(path: str = LIB_PATH):
         "ij_check": (st, [vp, vp]),
         "ij_derived": (st, [vp, ctypes.POINTER(ctypes.c_double)]),
         "ij_set_tiling": (st, [vp, i32, i32]),
+        "ij_autotune": (st, [vp, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
         "ij_batch_create": (st, [ctypes.POINTER(IJParams), i32, ctypes.POINTER(vp)]),
         "ij_batch_destroy": (None, [vp]),
         "ij_batch_last_error": (ctypes.c_char_p, [vp]),
@@ -205,6 +206,13 @@ class Sim:
 
     def set_tiling(self, waves_x: int = 0, rows_per_block: int = 0):
         self._check(self.L.ij_set_tiling(self.h, int(waves_x), int(rows_per_block)))
+
+    def autotune(self, trial_steps: int = 20, stream=None):
+        """Returns (waves_x, rows_per_block, ms per step)."""
+        w, r, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+        self._check(self.L.ij_autotune(self.h, int(trial_steps), _stream_ptr(stream), ctypes.byref(w),
+                                       ctypes.byref(r), ctypes.byref(ms)))
+        return int(w.value), int(r.value), float(ms.value)
 
     def attach(self, a, b):
         """Use two caller tensors (torch, uint8/float, contiguous, on the

@@ -138,6 +138,30 @@ def test_fused_kernel_equals_reference_kernels_bitwise(gpu_lib, name):
         assert np.array_equal(np.where(fl, _np(g), 0), np.where(fl, _np(gr), 0)), (waves, rows)
 
 
+def test_autotune_restores_state(gpu_lib):
+    """The autotuner's trial steps leave no trace: the distributions and the
+    step counter are as before, and later steps equal those of an untuned
+    run bit for bit (every tile shape computes the same bits)."""
+    p, wall, d = _case("nozzle_ragged")
+    a, b = gpu_lib.Sim(p, wall), gpu_lib.Sim(p, wall)
+    for s in (a, b):
+        s.init_distance(d)
+        s.step(7)
+    f0, g0 = a.state()
+    w, r, ms = a.autotune(4)
+    assert (w, r) in [(x, y) for x in (1, 2, 4) for y in (8, 16, 32, 64)] and ms > 0
+    f1, g1 = a.state()
+    assert a.t == 7
+    assert np.array_equal(_np(f0), _np(f1)) and np.array_equal(_np(g0), _np(g1))
+    a.step(21)
+    b.step(21)
+    fl = (wall == 0)[None]
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(np.where(fl, _np(x), 0), np.where(fl, _np(y), 0))
+    with pytest.raises(gpu_lib.LBMError):
+        a.autotune(1)
+
+
 def test_nozzle_64x256_1000_steps(oracle_mod, gpu_lib):
     """The 64 x 256 nozzle workload, pulse +1e-4 x 200, -5e-5 x 100, idle:
     fields within 1e-5 relative L2 of the FP64 oracle at every checkpoint."""
