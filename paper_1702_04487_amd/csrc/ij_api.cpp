@@ -265,6 +265,30 @@ ij_status build_plain(ij_sim* s)
     s->n_strips = n_strips;
     s->n_wide = n_wide;
     s->n_rb = (ny + s->rows_per_block - 1) / s->rows_per_block;
+    // plain tiles that hold a plain row; when some do not (a block of rows
+    // that all sit beside solid nodes, such as a nozzle channel), the plain
+    // launch runs over the list of the others
+    s->tile_plain.assign((size_t)s->n_rb * n_strips, 0);
+    std::vector<int4> pt;   // (strip, block, first column, 0)
+    for (int b = 0; b < s->n_rb; ++b)
+        for (int k = 0; k < n_strips; ++k) {
+            const int y0 = b * s->rows_per_block, y1 = std::min(ny, y0 + s->rows_per_block);
+            bool any = false;
+            for (int y = y0; y < y1 && !any; ++y) any = plain[(size_t)k * ny + y] != 0;
+            s->tile_plain[(size_t)b * n_strips + k] = any ? 1 : 0;
+            if (any) pt.push_back(make_int4(k, b, strip_x0(k), 0));
+        }
+    if (s->ptiles) (void)hipFree(s->ptiles);
+    s->ptiles = nullptr;
+    s->n_ptiles = -1;
+    if (!s->in_batch && !s->mixed_strips && pt.size() < s->tile_plain.size()) {
+        if (!pt.empty()) {
+            if (hipMalloc(&s->ptiles, pt.size() * sizeof(int4)) != hipSuccess)
+                return fail(s, IJ_ERR_OOM, "tile list allocation failed");
+            IJ_HIP(s, hipMemcpy(s->ptiles, pt.data(), pt.size() * sizeof(int4), hipMemcpyHostToDevice));
+        }
+        s->n_ptiles = (int)pt.size();
+    }
     s->strip_x0.resize((size_t)n_strips);
     for (int k = 0; k < n_strips; ++k) s->strip_x0[(size_t)k] = strip_x0(k);
     s->gtiles_host = gt;
@@ -335,6 +359,7 @@ void ij_host::destroy_sim(ij_sim* s)
     if (s->samples) (void)hipFree(s->samples);
     if (s->plain) (void)hipFree(s->plain);
     if (s->gtiles) (void)hipFree(s->gtiles);
+    if (s->ptiles) (void)hipFree(s->ptiles);
     delete s;
 }
 
@@ -520,8 +545,8 @@ ij_status ij_step(ij_sim* s, int64_t nsteps, void* stream)
         }
         s->K.fb = (float)pulse_value(s->p, s->t);
         hipError_t e = ij::launch_collide_fused(s->K, s->buf[s->cur], s->buf[1 - s->cur], s->wall, s->plain,
-                                                s->gtiles, s->n_gtiles, s->waves_x, s->rows_per_block, s->rows_general,
-                                                st);
+                                                s->ptiles, s->n_ptiles, s->gtiles, s->n_gtiles, s->waves_x,
+                                                s->rows_per_block, s->rows_general, st);
         if (e != hipSuccess) return hip_fail(s, e, "collide-stream kernel");
         s->cur = 1 - s->cur;
         s->t += 1;
@@ -716,8 +741,9 @@ ij_status ij_autotune(ij_sim* s, int32_t trial_steps, void* stream, int32_t* wav
         auto steps = [&](int n) {
             hipError_t r = hipSuccess;
             for (int k = 0; k < n && r == hipSuccess; ++k) {
-                r = ij::launch_collide_fused(s->K, s->buf[cur], s->buf[1 - cur], s->wall, s->plain, s->gtiles,
-                                             s->n_gtiles, s->waves_x, s->rows_per_block, s->rows_general, st);
+                r = ij::launch_collide_fused(s->K, s->buf[cur], s->buf[1 - cur], s->wall, s->plain, s->ptiles,
+                                             s->n_ptiles, s->gtiles, s->n_gtiles, s->waves_x, s->rows_per_block,
+                                             s->rows_general, st);
                 cur = 1 - cur;
             }
             return r;

@@ -140,9 +140,13 @@ ij_status build_tiles(ij_batch* b)
     std::vector<int4> lists[3];   // wide, tail, general
     for (size_t c = 0; c < b->sims.size(); ++c) {
         const ij_sim* s = b->sims[c];
+        // plain tiles that hold a plain row (a block of rows that all sit
+        // beside solid nodes, such as a nozzle channel, is the general
+        // launch's alone)
         for (int rb = 0; rb < s->n_rb; ++rb)
             for (int k = 0; k < s->n_strips; ++k)
-                lists[k < s->n_wide ? 0 : 1].push_back(make_int4((int)c, k, rb, s->strip_x0[(size_t)k]));
+                if (s->tile_plain[(size_t)rb * s->n_strips + k])
+                    lists[k < s->n_wide ? 0 : 1].push_back(make_int4((int)c, k, rb, s->strip_x0[(size_t)k]));
         for (const int4& g : s->gtiles_host) lists[2].push_back(make_int4((int)c, g.x, g.y, g.z));
     }
     int mg = 0;

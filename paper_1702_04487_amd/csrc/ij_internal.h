@@ -54,9 +54,12 @@ struct ij_sim {
     // tiles that hold the other rows (rebuilt with the wall or the tiling)
     uint8_t* plain = nullptr;
     int4* gtiles = nullptr;            // (strip, block, first column, 0) of the general launch
+    int4* ptiles = nullptr;            // plain tiles that hold a plain row (when listed)
+    int n_ptiles = -1;                 // their count; -1: the plain launch covers every tile
     int n_gtiles = 0;
     std::vector<int4> gtiles_host;
     std::vector<int> strip_x0;         // first column of each strip
+    std::vector<uint8_t> tile_plain;   // per (row block, strip) tile: holds a plain row
     int n_strips = 0, n_rb = 0;   // of the plain launch's tiling
     int n_wide = 0;               // strips 64 * waves_x wide; the others are 64 wide
     int rows_general = ij_host::kGeneralRowsShort;   // rows per general tile

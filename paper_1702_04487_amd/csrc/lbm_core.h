@@ -63,13 +63,16 @@ hipError_t launch_phi_ghost(const KParams& P, const float* A, const uint8_t* wal
 hipError_t launch_collide_ref(const KParams& P, const float* A, float* B, const uint8_t* wall,
                               const double* phi, hipStream_t st);
 // plain_rows: [n_strips][ny] bytes, 1 where the row of the strip is plain
-// (see the kernel).  The plain launch covers every tile of rows_per_block
-// rows of the strips of 64 * waves_x columns; general_tiles lists the
-// (strip, block of rows_general rows, first column, -) pieces, 64 columns
+// (see the kernel).  The plain launch covers the tiles of rows_per_block
+// rows of the strips of 64 * waves_x columns: every tile when n_plain_tiles
+// is negative, else the n_plain_tiles (strip, block, first column, -) tiles
+// listed in plain_tiles, row-block major (those that hold a plain row).  general_tiles lists
+// the (strip, block of rows_general rows, first column, -) pieces, 64 columns
 // wide, that hold other rows.
 hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, const uint8_t* wall,
-                                const uint8_t* plain_rows, const int4* general_tiles, int n_general_tiles,
-                                int waves_x, int rows_per_block, int rows_general, hipStream_t st);
+                                const uint8_t* plain_rows, const int4* plain_tiles, int n_plain_tiles,
+                                const int4* general_tiles, int n_general_tiles, int waves_x, int rows_per_block,
+                                int rows_general, hipStream_t st);
 hipError_t launch_init(const KParams& P, float* A, const uint8_t* wall, double* phi, const float* src,
                        int from_distance, const float* ux, const float* uy, const int2* ghost_list,
                        int n_ghost, hipStream_t st);

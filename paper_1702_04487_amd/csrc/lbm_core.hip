@@ -824,7 +824,14 @@ __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const floa
                                                            int rows_per_block, int n_strips,
                                                            int n_rowblocks)
 {
-    if (PLAIN) {
+    if (PLAIN && tile_list) {
+        // only the tiles that hold a plain row, listed row-block major as
+        // (strip, block, first column): XCD x (b % 8) takes the x-th
+        // contiguous run of the list
+        const int n = gridDim.x, b = blockIdx.x, xcd = b & 7;
+        const int4 tl = tile_list[xcd * (n >> 3) + min(xcd, n & 7) + (b >> 3)];
+        collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, tl.x, tl.z, tl.y, rows_per_block);
+    } else if (PLAIN) {
         const int ntiles = n_strips * n_rowblocks;
         int tile = blockIdx.x;
         if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
@@ -1308,31 +1315,35 @@ hipError_t launch_collide_ref(const KParams& P, const float* A, float* B, const 
 }
 
 hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, const uint8_t* wall,
-                                const uint8_t* plain_rows, const int4* general_tiles, int n_general_tiles,
-                                int waves_x, int rows_per_block, int rows_general, hipStream_t st)
+                                const uint8_t* plain_rows, const int4* plain_tiles, int n_plain_tiles,
+                                const int4* general_tiles, int n_general_tiles, int waves_x, int rows_per_block,
+                                int rows_general, hipStream_t st)
 {
     if (rows_per_block < 1 || rows_per_block > kMaxRowsPerBlock || rows_general < 1 ||
-        rows_general > kMaxRowsPerBlock)
+        rows_general > kMaxRowsPerBlock || (n_plain_tiles > 0 && !plain_tiles))
         return hipErrorInvalidValue;
     const int bw = 64 * waves_x;
     const int n_strips = (P.nx + bw - 1) / bw;
     const int n_rb = (P.ny + rows_per_block - 1) / rows_per_block;
-    const dim3 grid(n_strips * n_rb);
-    switch (waves_x) {
-    case 1:
-        hipLaunchKernelGGL((k_collide_fused<1, true>), grid, dim3(64), 0, st, P, A, B, wall, plain_rows,
-                           general_tiles, rows_per_block, n_strips, n_rb);
-        break;
-    case 2:
-        hipLaunchKernelGGL((k_collide_fused<2, true>), grid, dim3(128), 0, st, P, A, B, wall, plain_rows,
-                           general_tiles, rows_per_block, n_strips, n_rb);
-        break;
-    case 4:
-        hipLaunchKernelGGL((k_collide_fused<4, true>), grid, dim3(256), 0, st, P, A, B, wall, plain_rows,
-                           general_tiles, rows_per_block, n_strips, n_rb);
-        break;
-    default:
-        return hipErrorInvalidValue;
+    if (n_plain_tiles < 0) plain_tiles = nullptr;   // every tile
+    const dim3 grid(n_plain_tiles < 0 ? n_strips * n_rb : n_plain_tiles);
+    if (grid.x > 0) {
+        switch (waves_x) {
+        case 1:
+            hipLaunchKernelGGL((k_collide_fused<1, true>), grid, dim3(64), 0, st, P, A, B, wall, plain_rows,
+                               plain_tiles, rows_per_block, n_strips, n_rb);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_collide_fused<2, true>), grid, dim3(128), 0, st, P, A, B, wall, plain_rows,
+                               plain_tiles, rows_per_block, n_strips, n_rb);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_collide_fused<4, true>), grid, dim3(256), 0, st, P, A, B, wall, plain_rows,
+                               plain_tiles, rows_per_block, n_strips, n_rb);
+            break;
+        default:
+            return hipErrorInvalidValue;
+        }
     }
     // the general pieces are 64 columns wide: one wave each
     if (n_general_tiles > 0)
