@@ -230,10 +230,12 @@ ij_status build_plain(ij_sim* s)
             plain[(size_t)k * ny + y] = ok ? 1 : 0;
         }
     }
-    // general tiles, numbered row-block major (tile = block * n_strips +
-    // strip), are short (latency: a lone lattice leaves the device mostly
-    // idle) unless the lattice is one of a batch (throughput) and some strip
-    // has a long run of general rows
+    // general pieces: each run of non-plain rows of a strip, cut into
+    // pieces of at most kGeneralRows rows of near-equal height and 64
+    // columns (one wave); the pieces are short (latency: a lone lattice
+    // leaves the device mostly idle) unless the lattice is one of a batch
+    // (throughput) and some strip has a long run of general rows.  A piece
+    // without a fluid node has nothing to collide and is left out.
     int longest = 0;
     for (int k = 0; k < n_strips; ++k)
         for (int y = 0, run = 0; y < ny; ++y) {
@@ -241,27 +243,35 @@ ij_status build_plain(ij_sim* s)
             longest = std::max(longest, run);
         }
     const int kGeneralRows = s->in_batch && longest >= kGeneralTallRun ? kGeneralRowsTall : kGeneralRowsShort;
-    s->rows_general = kGeneralRows;
-    const int n_rb_g = (ny + kGeneralRows - 1) / kGeneralRows;
-    // general tiles: 64-column pieces (one wave each) of the (strip, block)
-    // pairs that hold a non-plain row; a piece without a fluid node in the
-    // block's rows has nothing to collide and is left out
-    std::vector<int4> gt;   // (strip, block, first column, 0)
-    for (int b = 0; b < n_rb_g; ++b)
-        for (int k = 0; k < n_strips; ++k) {
-            const int y0 = b * kGeneralRows, y1 = std::min(ny, y0 + kGeneralRows);
-            bool general = false;
-            for (int y = y0; y < y1 && !general; ++y) general = !plain[(size_t)k * ny + y];
-            if (!general) continue;
-            const int sx0 = strip_x0(k), sx1 = sx0 + strip_w(k);
-            for (int c0 = sx0; c0 < sx1; c0 += 64) {
-                const int c1 = std::min(sx1, c0 + 64);
-                bool fluid = false;
-                for (int y = y0; y < y1 && !fluid; ++y)
-                    for (int x = c0; x < c1 && !fluid; ++x) fluid = s->wall_host[(size_t)y * nx + x] == 0;
-                if (fluid) gt.push_back(make_int4(k, b, c0, 0));
+    std::vector<int4> gt;   // (strip, first row, first column, rows)
+    for (int k = 0; k < n_strips; ++k) {
+        const int sx0 = strip_x0(k), sx1 = sx0 + strip_w(k);
+        for (int r0 = 0; r0 < ny;) {
+            if (plain[(size_t)k * ny + r0]) {
+                ++r0;
+                continue;
             }
+            int r1 = r0;
+            while (r1 < ny && !plain[(size_t)k * ny + r1]) ++r1;
+            const int n = r1 - r0, parts = (n + kGeneralRows - 1) / kGeneralRows;
+            for (int j = 0, y0 = r0; j < parts; ++j) {
+                const int h = n / parts + (j < n % parts ? 1 : 0);
+                for (int c0 = sx0; c0 < sx1; c0 += 64) {
+                    const int c1 = std::min(sx1, c0 + 64);
+                    bool fluid = false;
+                    for (int y = y0; y < y0 + h && !fluid; ++y)
+                        for (int x = c0; x < c1 && !fluid; ++x) fluid = s->wall_host[(size_t)y * nx + x] == 0;
+                    if (fluid) gt.push_back(make_int4(k, y0, c0, h));
+                }
+                y0 += h;
+            }
+            r0 = r1;
         }
+    }
+    // row-major order: pieces that share halo rows run close together
+    std::stable_sort(gt.begin(), gt.end(), [](const int4& a, const int4& b) {
+        return a.y != b.y ? a.y < b.y : (a.x != b.x ? a.x < b.x : a.z < b.z);
+    });
     s->n_strips = n_strips;
     s->n_wide = n_wide;
     s->n_rb = (ny + s->rows_per_block - 1) / s->rows_per_block;
@@ -269,14 +279,14 @@ ij_status build_plain(ij_sim* s)
     // that all sit beside solid nodes, such as a nozzle channel), the plain
     // launch runs over the list of the others
     s->tile_plain.assign((size_t)s->n_rb * n_strips, 0);
-    std::vector<int4> pt;   // (strip, block, first column, 0)
+    std::vector<int4> pt;   // (strip, first row, first column, rows)
     for (int b = 0; b < s->n_rb; ++b)
         for (int k = 0; k < n_strips; ++k) {
             const int y0 = b * s->rows_per_block, y1 = std::min(ny, y0 + s->rows_per_block);
             bool any = false;
             for (int y = y0; y < y1 && !any; ++y) any = plain[(size_t)k * ny + y] != 0;
             s->tile_plain[(size_t)b * n_strips + k] = any ? 1 : 0;
-            if (any) pt.push_back(make_int4(k, b, strip_x0(k), 0));
+            if (any) pt.push_back(make_int4(k, y0, strip_x0(k), y1 - y0));
         }
     if (s->ptiles) (void)hipFree(s->ptiles);
     s->ptiles = nullptr;
@@ -546,7 +556,7 @@ ij_status ij_step(ij_sim* s, int64_t nsteps, void* stream)
         s->K.fb = (float)pulse_value(s->p, s->t);
         hipError_t e = ij::launch_collide_fused(s->K, s->buf[s->cur], s->buf[1 - s->cur], s->wall, s->plain,
                                                 s->ptiles, s->n_ptiles, s->gtiles, s->n_gtiles, s->waves_x,
-                                                s->rows_per_block, s->rows_general, st);
+                                                s->rows_per_block, st);
         if (e != hipSuccess) return hip_fail(s, e, "collide-stream kernel");
         s->cur = 1 - s->cur;
         s->t += 1;
@@ -743,7 +753,7 @@ ij_status ij_autotune(ij_sim* s, int32_t trial_steps, void* stream, int32_t* wav
             for (int k = 0; k < n && r == hipSuccess; ++k) {
                 r = ij::launch_collide_fused(s->K, s->buf[cur], s->buf[1 - cur], s->wall, s->plain, s->ptiles,
                                              s->n_ptiles, s->gtiles, s->n_gtiles, s->waves_x, s->rows_per_block,
-                                             s->rows_general, st);
+                                             st);
                 cur = 1 - cur;
             }
             return r;

@@ -145,9 +145,12 @@ ij_status build_tiles(ij_batch* b)
         // launch's alone)
         for (int rb = 0; rb < s->n_rb; ++rb)
             for (int k = 0; k < s->n_strips; ++k)
-                if (s->tile_plain[(size_t)rb * s->n_strips + k])
-                    lists[k < s->n_wide ? 0 : 1].push_back(make_int4((int)c, k, rb, s->strip_x0[(size_t)k]));
-        for (const int4& g : s->gtiles_host) lists[2].push_back(make_int4((int)c, g.x, g.y, g.z));
+                if (s->tile_plain[(size_t)rb * s->n_strips + k]) {
+                    const int y0 = rb * s->rows_per_block, h = std::min(s->ny - y0, s->rows_per_block);
+                    lists[k < s->n_wide ? 0 : 1].push_back(
+                        make_int4((int)c, k, y0 | (h << 16), s->strip_x0[(size_t)k]));
+                }
+        for (const int4& g : s->gtiles_host) lists[2].push_back(make_int4((int)c, g.x, g.y | (g.w << 16), g.z));
     }
     int mg = 0;
     for (const ij_sim* s : b->sims) mg = std::max(mg, s->n_ghost);
@@ -202,7 +205,6 @@ ij_status stage(ij_batch* b, hipStream_t st)
         r.rows = s->rows;
         r.ring = s->samples;
         r.n_ghost = s->n_ghost;
-        r.rows_general = s->rows_general;
         r.row0 = (int)s->p.diag_row0;
         r.a_min = (int)std::ceil(4.0 * s->p.width * s->p.width);
         r.t_pos = s->p.t_pos;
@@ -233,7 +235,7 @@ hipError_t one_step(ij_batch* b, int parity, bool diag, bool with_tick, hipStrea
         e = ij::launch_batch_diag(b->d_cases, (int)b->sims.size(), b->max_nx, b->max_ny, b->max_ghost, parity, b->d_t,
                                   b->d_nrec, b->d_active, st);
     if (e == hipSuccess)
-        e = ij::launch_batch_collide(b->T, b->d_cases, parity, b->d_t, b->d_active, b->waves_x, b->rows_per_block, st);
+        e = ij::launch_batch_collide(b->T, b->d_cases, parity, b->d_t, b->d_active, b->waves_x, st);
     if (e == hipSuccess && with_tick) e = ij::launch_batch_tick(b->d_t, st);
     return e;
 }

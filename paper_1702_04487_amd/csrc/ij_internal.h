@@ -62,7 +62,6 @@ struct ij_sim {
     std::vector<uint8_t> tile_plain;   // per (row block, strip) tile: holds a plain row
     int n_strips = 0, n_rb = 0;   // of the plain launch's tiling
     int n_wide = 0;               // strips 64 * waves_x wide; the others are 64 wide
-    int rows_general = ij_host::kGeneralRowsShort;   // rows per general tile
     bool mixed_strips = false;    // tail strips of 64 columns (batches)
     bool in_batch = false;        // owned and stepped by an ij_batch
     std::string err;

@@ -10,6 +10,7 @@ namespace ij {
 // followed by one plane of 16-bit words holding the bfloat16 remainder
 // g_0 - float(g_0) of the rest order-parameter population.
 constexpr int kFloatPlanes = 14;
+constexpr int kMaxRowsPerBlock = 1024;   // rows of one tile (LDS row flags)
 
 // Per-launch constants, derived on the host in double precision.  The
 // order-parameter path (phi, ghosts, stencils, mu, force) runs in double,
@@ -52,7 +53,6 @@ struct CaseRec {
     DiagRow* rows;          // [ny]
     SampleRec* ring;        // diagnostics records
     int n_ghost, row0, a_min;
-    int rows_general;       // rows per tile of the general launch
     int64_t t_pos, t_neg, t_idle;
     int periodic;
     double f_pos, f_neg, u_limit;
@@ -65,14 +65,15 @@ hipError_t launch_collide_ref(const KParams& P, const float* A, float* B, const 
 // plain_rows: [n_strips][ny] bytes, 1 where the row of the strip is plain
 // (see the kernel).  The plain launch covers the tiles of rows_per_block
 // rows of the strips of 64 * waves_x columns: every tile when n_plain_tiles
-// is negative, else the n_plain_tiles (strip, block, first column, -) tiles
-// listed in plain_tiles, row-block major (those that hold a plain row).  general_tiles lists
-// the (strip, block of rows_general rows, first column, -) pieces, 64 columns
-// wide, that hold other rows.
+// is negative, else the n_plain_tiles (strip, first row, first column, rows)
+// tiles listed in plain_tiles, row-block major (those that hold a plain
+// row).  general_tiles lists the (strip, first row, first column, rows)
+// pieces, 64 columns wide and at most kMaxRowsPerBlock rows, that hold the
+// other rows.
 hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, const uint8_t* wall,
                                 const uint8_t* plain_rows, const int4* plain_tiles, int n_plain_tiles,
                                 const int4* general_tiles, int n_general_tiles, int waves_x, int rows_per_block,
-                                int rows_general, hipStream_t st);
+                                hipStream_t st);
 hipError_t launch_init(const KParams& P, float* A, const uint8_t* wall, double* phi, const float* src,
                        int from_distance, const float* ux, const float* uy, const int2* ghost_list,
                        int n_ghost, hipStream_t st);
@@ -83,19 +84,19 @@ hipError_t launch_state_io(const KParams& P, float* A, const uint8_t* wall, floa
 hipError_t launch_diag(const KParams& P, const float* A, const uint8_t* wall, const double* phi, int row0,
                        int a_min, int64_t step, DiagRow* rows, SampleRec* out, hipStream_t st);
 
-// (case, strip, row block, first column) tiles of a batch: plain tiles
-// (rows_per_block rows) of the wide strips (workgroups of 64 * waves_x
-// lanes) and of the 64-column tail strips (one wave), and the 64-column
-// general pieces (one wave, each case's rows_general rows).  The plain
-// launches run grid_wide / grid_tail workgroups, each over a contiguous run
-// of tiles (a grid of one workgroup per tile when it equals the tile count).
+// (case, strip, first row | rows << 16, first column) tiles of a batch:
+// plain tiles of the wide strips (workgroups of 64 * waves_x lanes) and of
+// the 64-column tail strips (one wave), and the 64-column general pieces
+// (one wave); at most kMaxRowsPerBlock rows each.  The plain launches run
+// grid_wide / grid_tail workgroups, each over a contiguous run of tiles (a
+// grid of one workgroup per tile when it equals the tile count).
 struct BatchTiles {
     const int4 *wide, *tail, *gen;
     int n_wide, n_tail, n_gen;
     int grid_wide, grid_tail;
 };
 hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int64_t* t_dev,
-                                const int* active, int waves_x, int rows_per_block, hipStream_t st);
+                                const int* active, int waves_x, hipStream_t st);
 hipError_t launch_batch_tick(int64_t* t_dev, hipStream_t st);
 hipError_t launch_batch_set_time(int64_t* t_dev, int64_t t, hipStream_t st);
 hipError_t launch_batch_diag(const CaseRec* cases, int n_cases, int max_nx, int max_ny, int max_ghost, int parity,

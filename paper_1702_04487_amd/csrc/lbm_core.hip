@@ -501,7 +501,6 @@ __global__ void k_collide_ref(KParams P, const float* __restrict__ A, float* __r
 // open-row copies).  Each fluid node is collided by exactly one of the two
 // launches.  Tiles are numbered row-block major, so that the workgroups
 // resident at one time cover whole rows of the planes.
-constexpr int kMaxRowsPerBlock = 1024;
 
 // The value held by lane - 1 (from_left) or lane + 1 (from_right) of the
 // wave (DPP wave shifts); the lane at the wave edge gets its own value back.
@@ -516,14 +515,14 @@ __device__ __forceinline__ float from_right(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x130, 0xf, 0xf, false));   // wave_shl:1
 }
 
-// One tile (strip, row block) of the fused update.  fb is the body force of
-// the step.  Shared by the single-lattice and the batched kernels; it starts
-// with a barrier so that a workgroup may run several tiles in a row.
+// One tile (strip, rows [y0, y1)) of the fused update.  fb is the body force
+// of the step.  Shared by the single-lattice and the batched kernels; it
+// starts with a barrier so that a workgroup may run several tiles in a row.
 template <int NW, bool PLAIN>
 __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const float* __restrict__ A,
                                              float* __restrict__ B, const uint8_t* __restrict__ wall,
-                                             const uint8_t* __restrict__ plain_rows, int strip, int x0, int rb,
-                                             int rows_per_block)
+                                             const uint8_t* __restrict__ plain_rows, int strip, int x0, int y0,
+                                             int y1)
 {
     constexpr int BW = 64 * NW;
     // raw rows rr-3..rr are in use while row rr is processed; the last
@@ -539,8 +538,6 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
 
     __syncthreads();   // LDS of a previous tile of this workgroup is free
     const int wv = min(BW, P.nx - x0);
-    const int y0 = rb * rows_per_block;
-    const int y1 = min(P.ny, y0 + rows_per_block);
     const int t = threadIdx.x;
     const int lane = t & 63;
     const bool active = t < wv;
@@ -824,24 +821,34 @@ __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const floa
                                                            int rows_per_block, int n_strips,
                                                            int n_rowblocks)
 {
-    if (PLAIN && tile_list) {
-        // only the tiles that hold a plain row, listed row-block major as
-        // (strip, block, first column): XCD x (b % 8) takes the x-th
-        // contiguous run of the list
-        const int n = gridDim.x, b = blockIdx.x, xcd = b & 7;
-        const int4 tl = tile_list[xcd * (n >> 3) + min(xcd, n & 7) + (b >> 3)];
-        collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, tl.x, tl.z, tl.y, rows_per_block);
-    } else if (PLAIN) {
+    if (PLAIN) {
         const int ntiles = n_strips * n_rowblocks;
         int tile = blockIdx.x;
         if ((ntiles & 7) == 0) tile = (blockIdx.x & 7) * (ntiles >> 3) + (blockIdx.x >> 3);
         const int rb = tile / n_strips;
         const int strip = tile - rb * n_strips;
-        collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, strip, strip * 64 * NW, rb, rows_per_block);
+        const int y0 = rb * rows_per_block;
+        collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, strip, strip * 64 * NW, y0,
+                                min(P.ny, y0 + rows_per_block));
     } else {
-        const int4 tl = tile_list[blockIdx.x];
-        collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, tl.x, tl.z, tl.y, rows_per_block);
+        const int4 tl = tile_list[blockIdx.x];   // (strip, first row, first column, rows)
+        collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, tl.x, tl.z, tl.y, tl.y + tl.w);
     }
+}
+
+// The plain launch over a list of tiles (those that hold a plain row),
+// listed row-block major as (strip, first row, first column, rows): XCD x
+// (workgroup b % 8) takes the x-th contiguous run of the list.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_collide_listed(KParams P, const float* __restrict__ A,
+                                                            float* __restrict__ B,
+                                                            const uint8_t* __restrict__ wall,
+                                                            const uint8_t* __restrict__ plain_rows,
+                                                            const int4* __restrict__ tile_list)
+{
+    const int n = gridDim.x, b = blockIdx.x, xcd = b & 7;
+    const int4 tl = tile_list[xcd * (n >> 3) + min(xcd, n & 7) + (b >> 3)];
+    collide_tile<NW, true>(P, P.fb, A, B, wall, plain_rows, tl.x, tl.z, tl.y, tl.y + tl.w);
 }
 
 // ------------------------------------------------------------ init / moments
@@ -1216,25 +1223,26 @@ __device__ __forceinline__ double case_pulse(const CaseRec& c, int64_t t)
 }
 
 // Workgroup b runs tiles [b * per_wg, (b + 1) * per_wg) of the (case,
-// strip, row block, first column) list, in order (neighbouring tiles of a
-// case share their halo rows through the cache); a launch takes the tiles
-// of its own width (64 * NW columns).
+// strip, first row | rows << 16, first column) list, in order (neighbouring
+// tiles of a case share their halo rows through the cache); a launch takes
+// the tiles of its own width (64 * NW columns).
 template <int NW, bool PLAIN>
 __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __restrict__ cases,
                                                            const int4* __restrict__ tiles, int n_tiles,
                                                            int per_wg, int parity, const int64_t* __restrict__ t_dev,
-                                                           const int* __restrict__ active, int rows_per_block)
+                                                           const int* __restrict__ active)
 {
     const int64_t t = *t_dev;
     const int i0 = blockIdx.x * per_wg, i1 = min(n_tiles, i0 + per_wg);
     for (int i = i0; i < i1; ++i) {
-        const int4 tl = tiles[i];   // (case, strip, row block, first column)
+        const int4 tl = tiles[i];   // (case, strip, first row | rows << 16, first column)
         if (!active[tl.x]) continue;
         const CaseRec& R = cases[tl.x];
         const KParams P = R.P;
         const float fb = (float)case_pulse(R, t);
-        collide_tile<NW, PLAIN>(P, fb, R.buf[parity], R.buf[1 - parity], R.wall, R.plain, tl.y, tl.w, tl.z,
-                                PLAIN ? rows_per_block : R.rows_general);
+        const int y0 = tl.z & 0xffff;
+        collide_tile<NW, PLAIN>(P, fb, R.buf[parity], R.buf[1 - parity], R.wall, R.plain, tl.y, tl.w, y0,
+                                y0 + (tl.z >> 16));
     }
 }
 
@@ -1317,29 +1325,42 @@ hipError_t launch_collide_ref(const KParams& P, const float* A, float* B, const 
 hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, const uint8_t* wall,
                                 const uint8_t* plain_rows, const int4* plain_tiles, int n_plain_tiles,
                                 const int4* general_tiles, int n_general_tiles, int waves_x, int rows_per_block,
-                                int rows_general, hipStream_t st)
+                                hipStream_t st)
 {
-    if (rows_per_block < 1 || rows_per_block > kMaxRowsPerBlock || rows_general < 1 ||
-        rows_general > kMaxRowsPerBlock || (n_plain_tiles > 0 && !plain_tiles))
+    if (rows_per_block < 1 || rows_per_block > kMaxRowsPerBlock || (n_plain_tiles > 0 && !plain_tiles))
         return hipErrorInvalidValue;
     const int bw = 64 * waves_x;
     const int n_strips = (P.nx + bw - 1) / bw;
     const int n_rb = (P.ny + rows_per_block - 1) / rows_per_block;
-    if (n_plain_tiles < 0) plain_tiles = nullptr;   // every tile
-    const dim3 grid(n_plain_tiles < 0 ? n_strips * n_rb : n_plain_tiles);
-    if (grid.x > 0) {
+    if (n_plain_tiles < 0) {   // every tile
+        const dim3 grid(n_strips * n_rb);
         switch (waves_x) {
         case 1:
             hipLaunchKernelGGL((k_collide_fused<1, true>), grid, dim3(64), 0, st, P, A, B, wall, plain_rows,
-                               plain_tiles, rows_per_block, n_strips, n_rb);
+                               nullptr, rows_per_block, n_strips, n_rb);
             break;
         case 2:
             hipLaunchKernelGGL((k_collide_fused<2, true>), grid, dim3(128), 0, st, P, A, B, wall, plain_rows,
-                               plain_tiles, rows_per_block, n_strips, n_rb);
+                               nullptr, rows_per_block, n_strips, n_rb);
             break;
         case 4:
             hipLaunchKernelGGL((k_collide_fused<4, true>), grid, dim3(256), 0, st, P, A, B, wall, plain_rows,
-                               plain_tiles, rows_per_block, n_strips, n_rb);
+                               nullptr, rows_per_block, n_strips, n_rb);
+            break;
+        default:
+            return hipErrorInvalidValue;
+        }
+    } else if (n_plain_tiles > 0) {
+        const dim3 grid(n_plain_tiles);
+        switch (waves_x) {
+        case 1:
+            hipLaunchKernelGGL((k_collide_listed<1>), grid, dim3(64), 0, st, P, A, B, wall, plain_rows, plain_tiles);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_collide_listed<2>), grid, dim3(128), 0, st, P, A, B, wall, plain_rows, plain_tiles);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_collide_listed<4>), grid, dim3(256), 0, st, P, A, B, wall, plain_rows, plain_tiles);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1348,7 +1369,7 @@ hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, cons
     // the general pieces are 64 columns wide: one wave each
     if (n_general_tiles > 0)
         hipLaunchKernelGGL((k_collide_fused<1, false>), dim3(n_general_tiles), dim3(64), 0, st, P, A, B, wall,
-                           plain_rows, general_tiles, rows_general, n_strips, n_rb);
+                           plain_rows, general_tiles, 0, n_strips, n_rb);
     return hipGetLastError();
 }
 
@@ -1368,9 +1389,9 @@ int batch_resident_workgroups(int waves_x)
 }
 
 hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int64_t* t_dev,
-                                const int* active, int waves_x, int rows_per_block, hipStream_t st)
+                                const int* active, int waves_x, hipStream_t st)
 {
-    if (rows_per_block < 1 || rows_per_block > kMaxRowsPerBlock || (parity & ~1)) return hipErrorInvalidValue;
+    if (parity & ~1) return hipErrorInvalidValue;
     // plain launches (one per strip width; persistent when the grid is
     // smaller than the tile count), then the general pieces
     auto runs = [&](int n, int grid, int& per_wg) {
@@ -1383,20 +1404,20 @@ hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int p
     const int gt = runs(T.n_tail, T.grid_tail, pt);
     if (gt > 0)
         hipLaunchKernelGGL((k_batch_collide<1, true>), dim3(gt), dim3(64), 0, st, cases, T.tail, T.n_tail, pt,
-                           parity, t_dev, active, rows_per_block);
+                           parity, t_dev, active);
     if (gw > 0) {
         switch (waves_x) {
         case 1:
             hipLaunchKernelGGL((k_batch_collide<1, true>), dim3(gw), dim3(64), 0, st, cases, T.wide, T.n_wide, pw,
-                               parity, t_dev, active, rows_per_block);
+                               parity, t_dev, active);
             break;
         case 2:
             hipLaunchKernelGGL((k_batch_collide<2, true>), dim3(gw), dim3(128), 0, st, cases, T.wide, T.n_wide, pw,
-                               parity, t_dev, active, rows_per_block);
+                               parity, t_dev, active);
             break;
         case 4:
             hipLaunchKernelGGL((k_batch_collide<4, true>), dim3(gw), dim3(256), 0, st, cases, T.wide, T.n_wide, pw,
-                               parity, t_dev, active, rows_per_block);
+                               parity, t_dev, active);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1404,7 +1425,7 @@ hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int p
     }
     if (T.n_gen > 0)
         hipLaunchKernelGGL((k_batch_collide<1, false>), dim3(T.n_gen), dim3(64), 0, st, cases, T.gen, T.n_gen, 1,
-                           parity, t_dev, active, 0);
+                           parity, t_dev, active);
     return hipGetLastError();
 }
 

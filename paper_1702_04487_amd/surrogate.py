@@ -41,6 +41,7 @@ INPUT_NAMES = ("theta", "sigma", "f_pos", "f_neg", "t_pos", "t_neg", "t_idle")
 TARGET_NAMES = ("breakup_step", "v_drop", "vol_drop", "satellite")
 U_CAP = 0.2
 GAMMA_SIGMA_MAX = 0.01
+NO_BREAKUP_BAND = 0.02   # relative distance of a predicted breakup step from the horizon read as none
 
 
 def _log(msg: str) -> None:
@@ -184,10 +185,11 @@ class Surrogate:
         self.threshold = None
 
     def fit(self, x: np.ndarray, y: np.ndarray, steps: int = 4000, batch: int = 256, lr: float = 2e-3,
-            seed: int = 99):
+            seed: int = 99, horizon: int = HORIZON):
         if ROOT not in sys.path:
             sys.path.insert(0, ROOT)
         import workloads as W
+        self.horizon = float(horizon)
         self.x_mean, self.x_std = x.mean(axis=0), x.std(axis=0) + 1e-12
         self.y_mean, self.y_std = y[:, :3].mean(axis=0), y[:, :3].std(axis=0) + 1e-12
         self.net.set_scaling(self.x_mean, self.x_std, self.y_mean, self.y_std)
@@ -200,10 +202,16 @@ class Surrogate:
     def predict(self, x: np.ndarray):
         """(mean [n, 4], normalised spread [n]) on the host: the spread is the
         largest member standard deviation of breakup step and drop velocity
-        in units of the training targets' spread."""
+        in units of the training targets' spread.  A mean breakup step within
+        NO_BREAKUP_BAND of the horizon is read as no breakup and answered
+        exactly as such (t_b = horizon, v = V = 0, no satellite): a case
+        without a drop is then not charged the regression noise of v around
+        zero."""
         mean, spread = self.net.predict(x)
         mean = mean.cpu().numpy().astype(np.float64)
         spread = spread.cpu().numpy().astype(np.float64)
+        none = mean[:, 0] >= self.horizon * (1.0 - NO_BREAKUP_BAND)
+        mean[none] = [self.horizon, 0.0, 0.0, 0.0]
         return mean, np.max(spread[:, :2] / self.y_std[:2], axis=1)
 
 
@@ -216,14 +224,23 @@ def errors(pred: np.ndarray, y: np.ndarray, v_scale: float = 0.01):
     return et, ev
 
 
-def calibrate(spread: np.ndarray, et: np.ndarray, ev: np.ndarray, tol: float = 0.02) -> float:
+def calibrate(spread: np.ndarray, et: np.ndarray, ev: np.ndarray, tol: float = 0.02, z: float = 1.645) -> float:
     """Largest spread threshold whose answered cases (spread <= threshold)
-    keep the mean of both errors within tol (0 if none does)."""
+    keep both mean errors within tol with one-sided confidence: the mean
+    plus z standard errors of the mean (z = 1.645: 95 %) must not exceed
+    tol (0 if no threshold qualifies).  The bound, rather than the sample
+    mean, keeps the choice of the largest qualifying threshold from
+    overfitting the calibration cases."""
     order = np.argsort(spread)
-    ce_t = np.cumsum(et[order]) / np.arange(1, len(order) + 1)
-    ce_v = np.cumsum(ev[order]) / np.arange(1, len(order) + 1)
-    ok = np.nonzero((ce_t <= tol) & (ce_v <= tol))[0]
-    return float(spread[order][ok[-1]]) if len(ok) else 0.0
+    k = np.arange(1, len(order) + 1)
+    ok = np.ones(len(order), bool)
+    for e in (et, ev):
+        e = np.asarray(e, np.float64)[order]
+        m = np.cumsum(e) / k
+        var = np.maximum(np.cumsum(e * e) / k - m * m, 0.0)
+        ok &= m + z * np.sqrt(var / k) <= tol
+    idx = np.nonzero(ok)[0]
+    return float(spread[order][idx[-1]]) if len(idx) else 0.0
 
 
 def main(argv: Optional[list] = None) -> int:

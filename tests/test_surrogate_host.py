@@ -53,5 +53,29 @@ def test_errors_and_calibration():
     spread = np.array([0.1, 0.3, 0.5, 0.05])
     # ordered by spread: cases 3, 0, 1, 2; running means of e_t: 0, .005, .0033, .0525;
     # of e_v: 0, .005, .0367 -> the last admissible prefix ends at case 0
+    # (the bound on the two-case prefix: .005 + 1.645 * .005 / sqrt 2 = .0108)
     assert S.calibrate(spread, et, ev, tol=0.02) == 0.1
     assert S.calibrate(spread, et + 1.0, ev, tol=0.02) == 0.0
+    # a prefix whose mean is within tol but whose bound is not is refused:
+    # errors 0, .039 have mean .0195 and bound .0195 + 1.645 * .0195 / sqrt 2 = .042
+    s2, z2 = np.array([0.1, 0.2]), np.zeros(2)
+    assert S.calibrate(s2, np.array([0.0, 0.039]), z2, tol=0.02) == 0.1
+    assert S.calibrate(s2, np.array([0.0, 0.039]), z2, tol=0.02, z=0.0) == 0.2
+
+
+def test_predict_reads_breakup_near_horizon_as_none():
+    """A mean breakup step within the band below the horizon is answered as
+    no breakup exactly; other rows and the spread pass through."""
+    import torch
+
+    class _Net:
+        def predict(self, x):
+            mean = torch.tensor([[23700.0, 0.0003, 12.0, 0.1], [23000.0, 0.012, 9000.0, 0.2]])
+            return mean, torch.tensor([[2.0, 0.004, 0.0, 0.0], [4.0, 0.002, 0.0, 0.0]])
+
+    sur = S.Surrogate.__new__(S.Surrogate)
+    sur.net, sur.horizon, sur.y_std = _Net(), 24000.0, np.array([10.0, 0.01, 1.0])
+    mean, spread = sur.predict(np.zeros((2, 7)))
+    assert list(mean[0]) == [24000.0, 0.0, 0.0, 0.0]              # 23700 >= 0.98 * 24000
+    assert np.allclose(mean[1], [23000.0, 0.012, 9000.0, 0.2])    # below the band: unchanged
+    assert np.allclose(spread, [0.4, 0.4])                         # max(2/10, .004/.01), max(4/10, .002/.01)
