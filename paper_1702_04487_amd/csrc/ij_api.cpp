@@ -230,12 +230,13 @@ ij_status build_plain(ij_sim* s)
             plain[(size_t)k * ny + y] = ok ? 1 : 0;
         }
     }
-    // general pieces: each run of non-plain rows of a strip, cut into
-    // pieces of at most kGeneralRows rows of near-equal height and 64
-    // columns (one wave); the pieces are short (latency: a lone lattice
-    // leaves the device mostly idle) unless the lattice is one of a batch
-    // (throughput) and some strip has a long run of general rows.  A piece
-    // without a fluid node has nothing to collide and is left out.
+    // general pieces, 64 columns wide (one wave): in each 64-column piece of
+    // a strip, the runs of rows that are not plain and hold a fluid node in
+    // the piece's columns, cut into pieces of at most kGeneralRows rows of
+    // near-equal height.  A lone such row (an open row, the row above a
+    // nozzle plate) is one piece of one row.  Pieces are short (latency: a
+    // lone lattice leaves the device mostly idle) unless the lattice is one
+    // of a batch (throughput) and some strip has a long run of general rows.
     int longest = 0;
     for (int k = 0; k < n_strips; ++k)
         for (int y = 0, run = 0; y < ny; ++y) {
@@ -244,28 +245,32 @@ ij_status build_plain(ij_sim* s)
         }
     const int kGeneralRows = s->in_batch && longest >= kGeneralTallRun ? kGeneralRowsTall : kGeneralRowsShort;
     std::vector<int4> gt;   // (strip, first row, first column, rows)
+    std::vector<uint8_t> take((size_t)ny);
     for (int k = 0; k < n_strips; ++k) {
         const int sx0 = strip_x0(k), sx1 = sx0 + strip_w(k);
-        for (int r0 = 0; r0 < ny;) {
-            if (plain[(size_t)k * ny + r0]) {
-                ++r0;
-                continue;
+        for (int c0 = sx0; c0 < sx1; c0 += 64) {
+            const int c1 = std::min(sx1, c0 + 64);
+            for (int y = 0; y < ny; ++y) {
+                bool fluid = false;
+                if (!plain[(size_t)k * ny + y])
+                    for (int x = c0; x < c1 && !fluid; ++x) fluid = s->wall_host[(size_t)y * nx + x] == 0;
+                take[(size_t)y] = fluid ? 1 : 0;
             }
-            int r1 = r0;
-            while (r1 < ny && !plain[(size_t)k * ny + r1]) ++r1;
-            const int n = r1 - r0, parts = (n + kGeneralRows - 1) / kGeneralRows;
-            for (int j = 0, y0 = r0; j < parts; ++j) {
-                const int h = n / parts + (j < n % parts ? 1 : 0);
-                for (int c0 = sx0; c0 < sx1; c0 += 64) {
-                    const int c1 = std::min(sx1, c0 + 64);
-                    bool fluid = false;
-                    for (int y = y0; y < y0 + h && !fluid; ++y)
-                        for (int x = c0; x < c1 && !fluid; ++x) fluid = s->wall_host[(size_t)y * nx + x] == 0;
-                    if (fluid) gt.push_back(make_int4(k, y0, c0, h));
+            for (int r0 = 0; r0 < ny;) {
+                if (!take[(size_t)r0]) {
+                    ++r0;
+                    continue;
                 }
-                y0 += h;
+                int r1 = r0;
+                while (r1 < ny && take[(size_t)r1]) ++r1;
+                const int n = r1 - r0, parts = (n + kGeneralRows - 1) / kGeneralRows;
+                for (int j = 0, y0 = r0; j < parts; ++j) {
+                    const int h = n / parts + (j < n % parts ? 1 : 0);
+                    gt.push_back(make_int4(k, y0, c0, h));
+                    y0 += h;
+                }
+                r0 = r1;
             }
-            r0 = r1;
         }
     }
     // row-major order: pieces that share halo rows run close together
