@@ -42,8 +42,8 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1702_04487_amd", "csrc", "lbm_core.hip
 # kernel source with this SHA-256 only; for any other it is reported as null.
 MEASURED_TRAFFIC = {
     "kernel_source_sha256": "c822945906d053e190f5ebc9cd7260a311b3ac67478768e76920b9d87472d3b8",
-    "read_bytes": 2117147330,
-    "write_bytes": 1978724925,
+    "read_bytes": 2118477378,
+    "write_bytes": 1978729936,
 }
 COPY_CEILING_GBS = 5148.4  # best read+write rate of copy_calib on MI355X (float4, 65536 x 256)
 
