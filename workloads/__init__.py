@@ -180,6 +180,88 @@ def config_nozzle_single() -> dict:
                 distance=None, row0=L, steps=60000, nozzle=(x0, w, L))
 
 
+class PaperUnits:
+    """Lattice <-> physical units of the paper's validation run (Results,
+    "Reproducing the experiment"): silicone oil of density 930 kg/m^3,
+    viscosity 9.3 mPa s, nozzle radius 15 um = 40 nodes.  The length unit
+    follows from the radius, the time unit from the kinematic viscosity
+    nu = (tau_n - 1/2) / 3 of the lattice (tau_n = 0.85, so nu = 0.1167; the
+    0.17 printed beside it would put sigma = 1.08 at 9.3 mN/m instead of the
+    oil's 20.2), the mass unit from the liquid density (1000 in the
+    lattice)."""
+
+    def __init__(self, radius_um: float = 15.0, radius_lu: float = 40.0, tau_n: float = 0.85,
+                 rho_phys: float = 930.0, mu_phys: float = 9.3e-3, rho_lu: float = 1000.0):
+        self.dx = radius_um * 1e-6 / radius_lu                       # m per node
+        self.nu_lu = (tau_n - 0.5) / 3.0
+        self.dt = self.nu_lu * self.dx ** 2 / (mu_phys / rho_phys)     # s per step
+        self.dm = rho_phys / rho_lu * self.dx ** 3                     # kg per lattice mass unit
+
+    def steps(self, microseconds: float) -> int:
+        return int(round(microseconds * 1e-6 / self.dt))
+
+    def microseconds(self, steps: float) -> float:
+        return steps * self.dt * 1e6
+
+    def velocity_ms(self, u_lu: float) -> float:
+        return u_lu * self.dx / self.dt
+
+    def sigma_lu(self, sigma_mn_per_m: float) -> float:
+        # N/m = kg / s^2
+        return sigma_mn_per_m * 1e-3 * self.dt ** 2 / self.dm
+
+    def sigma_mn_per_m(self, sigma_lu: float) -> float:
+        return sigma_lu * self.dm / self.dt ** 2 * 1e3
+
+
+# Mobility of the paper preset (the paper does not print it).  The
+# Cahn-Hilliard diffusivity of a bulk phase is theta_M * d(mu)/d(phi) =
+# theta_M * 8 beta phi*^2 = theta_M * 6 sigma / (W phi*^2); at phi* = 499.5 a
+# mobility of order one leaves the interface practically frozen (four orders
+# below the presets above).  GAMMA_PAPER gives the diffusivity of the presets
+# above (sigma 0.01, W 4, phi* 0.45, Gamma 1, tau_phi 1: 8.2e-3) at sigma
+# 1.08, W 3, tau_phi 0.8.  For other sigma the mobility scales as 1.08 /
+# sigma, which keeps that diffusivity and theta_M * kappa (the explicit
+# scheme's fourth-order term) fixed: at a fixed Gamma, theta_M kappa pi^4
+# grows from 0.45 at sigma 1.08 to 1.95 at 85 mN/m, and the runs above
+# 30 mN/m went unstable within 300 steps.
+GAMMA_PAPER = 1.07e4
+
+# Pulse amplitudes of the paper preset (not printed in the paper): a push and
+# a 16 % stronger pull that pinch the ejected filament off at about 42 us at
+# 90 degrees, and stay within the speed guard over the whole 20-85 mN/m range
+# (a 0.07 / 0.08 pulse breaks at 45 us but trips the guard from 50 mN/m up).
+F_POS_PAPER, F_NEG_PAPER = 5.0e-2, 5.8e-2
+
+
+def config_paper(theta: float = 90.0, sigma_mn_per_m: float = None, f_pos: float = F_POS_PAPER,
+                 f_neg: float = F_NEG_PAPER, gamma: float = None, pulse_us=(5.0, 3.0, 8.0),
+                 periodic_pulse: bool = False, steps_us: float = 130.0, theta_outer: float = 90.0) -> dict:
+    """The paper's validation lattice: 200 wide and 800 long (jet along y),
+    nozzle 120 high with radius 40 (an 80-wide channel), densities 1000/1
+    (phi* = 499.5), W = 3, tau_n = 0.85, tau_phi = 0.8, sigma = 1.08 (or the
+    value of sigma_mn_per_m in physical units), periodic sides, open top and
+    bottom rows, contact angle theta on the nozzle inner wall.  Pulse: +5 us,
+    -3 us, 8 us idle (Fig. 1), converted with PaperUnits.  The force
+    amplitudes and the mobility are not printed in the paper: f_pos, f_neg
+    and gamma (default GAMMA_PAPER * 1.08 / sigma) are this preset's
+    choice."""
+    u = PaperUnits()
+    nx, ny, L, w = 200, 800, 120, 80
+    x0 = (nx - w) // 2
+    sigma = 1.08 if sigma_mn_per_m is None else u.sigma_lu(sigma_mn_per_m)
+    if gamma is None:
+        gamma = GAMMA_PAPER * 1.08 / sigma
+    tp, tn, ti = (u.steps(t) for t in pulse_us)
+    p = base_params(nx, ny, force_rows=L, t_pos=tp, t_neg=tn, t_idle=ti, periodic_pulse=int(periodic_pulse),
+                    rho_ink=1000.0, rho_amb=1.0, sigma=sigma, width=3.0, gamma=gamma, tau_ink=0.85,
+                    tau_amb=0.85, tau_phi=0.8, theta_inner=theta, theta_outer=theta_outer, f_pos=f_pos,
+                    f_neg=f_neg)
+    return dict(name=f"paper_{nx}x{ny}", params=p, wall=nozzle_wall(nx, ny, x0, w, L),
+                distance=meniscus_distance(nx, ny, L), row0=L, steps=u.steps(steps_us), nozzle=(x0, w, L),
+                units=u)
+
+
 def config_droplet_field(nx: int = 2048, ny: int = 16384, seed: int = 0,
                          with_distance: bool = True) -> dict:
     """Roofline stress: seeded disc field (radii 8-64, ink area >= 25 %),
