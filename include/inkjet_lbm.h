@@ -86,6 +86,9 @@ typedef struct ij_sample {
     int64_t largest_count;     /* ink nodes (phi > 0) of the largest one */
     double largest_uy;         /* sum of u_y over those nodes */
     int64_t largest_top;       /* its highest row (-1: none) */
+    int64_t largest_bottom;    /* its lowest row (-1: none) */
+    double head_uy, tail_uy;   /* mean u_y of its ink in its top / bottom ceil(W)
+                                  rows: the head and tail velocities of Fig. 3 */
 } ij_sample;
 
 /* Summary of the samples recorded so far. */
@@ -98,6 +101,8 @@ typedef struct ij_diag {
     int64_t satellite;         /* >= 2 detached drops at t_b+2000 */
     int64_t unstable_step;     /* first sample failing the guard, -1: none */
     ij_sample last;            /* the latest sample */
+    int64_t drop_len;          /* rows spanned by the largest drop at t_b: the
+                                  drop and its filament at breakup (Fig. 4) */
 } ij_diag;
 
 typedef struct ij_sim ij_sim;

@@ -11,6 +11,7 @@ Parameter dictionaries use the keys of :data:`PARAM_KEYS`; geometry is a
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from typing import Optional
@@ -195,11 +196,19 @@ class OracleSim:
 # are measured; this follows the row-segment reading stated in the design notes.
 # --------------------------------------------------------------------------
 
-def segments(row_count: np.ndarray, row_uy: np.ndarray, row0: int, a_min: float) -> dict:
+def band_rows(width: float) -> int:
+    """Rows of the head and of the tail of a drop: one interface width."""
+    return max(1, int(math.ceil(width - 1e-9)))
+
+
+def segments(row_count: np.ndarray, row_uy: np.ndarray, row0: int, a_min: float, band: int = 1) -> dict:
     """Split the rows y >= row0 into maximal runs with ink.  The run that
     contains row0 (the nozzle exit row) is attached; every other run with at
     least a_min ink nodes is a detached drop.  Returns the number of detached
-    drops and the ink count and summed u_y of the largest one."""
+    drops and, for the largest one, its ink count, summed u_y, highest and
+    lowest rows, and the mean u_y of the ink in its top `band` rows (head)
+    and in its bottom `band` rows (tail) -- the head and tail velocities of
+    Fig. 3."""
     runs = []
     y = row0
     ny = len(row_count)
@@ -220,10 +229,14 @@ def segments(row_count: np.ndarray, row_uy: np.ndarray, row0: int, a_min: float)
         if c >= a_min:
             detached.append((c, float(np.sum(row_uy[a:b])), a, b))
     out = {"n_detached": len(detached), "largest_count": 0, "largest_uy": 0.0,
-           "largest_top": -1}
+           "largest_top": -1, "largest_bottom": -1, "head_uy": 0.0, "tail_uy": 0.0}
     if detached:
         best = max(detached, key=lambda r: (r[0], -r[2]))
-        out.update(largest_count=best[0], largest_uy=best[1], largest_top=best[3] - 1)
+        a, b = best[2], best[3]
+        h0, t1 = max(a, b - band), min(b, a + band)
+        out.update(largest_count=best[0], largest_uy=best[1], largest_top=b - 1, largest_bottom=a,
+                   head_uy=float(np.sum(row_uy[h0:b]) / np.sum(row_count[h0:b])),
+                   tail_uy=float(np.sum(row_uy[a:t1]) / np.sum(row_count[a:t1])))
     return out
 
 
@@ -236,15 +249,18 @@ def breakup_summary(samples: list, ny: int, width: float, t_window=(1000, 3000),
     [t_b + 1000, t_b + 3000] (stopping once the drop top comes within 2W of
     the last row); V_drop is its ink count and the satellite flag is set when
     two or more drops are detached at the first sample at or after
-    t_b + 2000."""
+    t_b + 2000.  drop_len is the rows spanned by the largest drop at t_b:
+    the drop with its filament at breakup (Fig. 4)."""
     tb = -1
     for s in samples:
         if s["n_detached"] > 0:
             tb = s["step"]
             break
-    out = {"breakup_step": tb, "v_drop": float("nan"), "vol_drop": 0, "satellite": 0}
+    out = {"breakup_step": tb, "v_drop": float("nan"), "vol_drop": 0, "satellite": 0, "drop_len": 0}
     if tb < 0:
         return out
+    first = next(s for s in samples if s["step"] == tb)
+    out["drop_len"] = int(first["largest_top"] - first["largest_bottom"] + 1)
     vs = []
     for s in samples:
         if tb + t_window[0] <= s["step"] <= tb + t_window[1] and s["largest_count"] > 0:

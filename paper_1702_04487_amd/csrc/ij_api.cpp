@@ -326,6 +326,8 @@ ij_status build_plain(ij_sim* s)
 // above this limit
 double u_limit(const ij_params& p) { return p.u_limit > 0 ? p.u_limit : 0.3; }
 
+int diag_band(double width) { return std::max(1, (int)std::ceil(width - 1e-9)); }
+
 ij_status drain_samples(ij_sim* s, hipStream_t st)
 {
     if (s->n_dev_samples == 0) return IJ_OK;
@@ -353,8 +355,8 @@ ij_status record_sample(ij_sim* s, hipStream_t st)
     hipError_t e = ij::launch_phi_ghost(s->K, s->buf[s->cur], s->wall, s->phi, s->ghost, s->n_ghost, st);
     if (e != hipSuccess) return hip_fail(s, e, "phi/ghost kernels");
     const int a_min = (int)std::ceil(4.0 * s->p.width * s->p.width);
-    e = ij::launch_diag(s->K, s->buf[s->cur], s->wall, s->phi, (int)s->p.diag_row0, a_min, s->t, s->rows,
-                        s->samples + s->n_dev_samples, st);
+    e = ij::launch_diag(s->K, s->buf[s->cur], s->wall, s->phi, (int)s->p.diag_row0, a_min, diag_band(s->p.width),
+                        s->t, s->rows, s->samples + s->n_dev_samples, st);
     if (e != hipSuccess) return hip_fail(s, e, "diagnostics kernels");
     s->n_dev_samples += 1;
     return IJ_OK;
@@ -677,6 +679,7 @@ ij_status ij_get_diagnostics(ij_sim* s, ij_diag* out, void* stream)
     out->breakup_step = -1;
     out->v_drop = NAN;
     out->last.largest_top = -1;
+    out->last.largest_bottom = -1;
     if (s->host_samples.empty()) return IJ_OK;
     out->last = s->host_samples.back();
     // breakup: first sample with a detached drop
@@ -684,6 +687,7 @@ ij_status ij_get_diagnostics(ij_sim* s, ij_diag* out, void* stream)
     for (const auto& x : s->host_samples)
         if (x.n_detached > 0) {
             tb = x.step;
+            out->drop_len = x.largest_top - x.largest_bottom + 1;   // drop and filament at breakup
             break;
         }
     out->breakup_step = tb;

@@ -207,6 +207,7 @@ ij_status stage(ij_batch* b, hipStream_t st)
         r.n_ghost = s->n_ghost;
         r.row0 = (int)s->p.diag_row0;
         r.a_min = (int)std::ceil(4.0 * s->p.width * s->p.width);
+        r.band = diag_band(s->p.width);
         r.t_pos = s->p.t_pos;
         r.t_neg = s->p.t_neg;
         r.t_idle = s->p.t_idle;

@@ -76,6 +76,8 @@ std::string validate(const ij_params& p);
 ij_status build_plain(ij_sim* s);
 ij_status drain_samples(ij_sim* s, hipStream_t st);
 double u_limit(const ij_params& p);
+// rows of the head and of the tail of a drop (one interface width)
+int diag_band(double width);
 void destroy_sim(ij_sim* s);   // frees a handle whatever its owner
 
 }  // namespace ij_host

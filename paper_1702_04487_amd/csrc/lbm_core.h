@@ -40,6 +40,8 @@ struct SampleRec {
     int64_t nan_count, n_detached, largest_count;
     double largest_uy;
     int64_t largest_top;
+    int64_t largest_bottom;
+    double head_uy, tail_uy;
 };
 
 // One lattice of a batch as the batched kernels see it (device memory).
@@ -52,7 +54,7 @@ struct CaseRec {
     const int2* ghost;      // solid nodes that touch fluid
     DiagRow* rows;          // [ny]
     SampleRec* ring;        // diagnostics records
-    int n_ghost, row0, a_min;
+    int n_ghost, row0, a_min, band;
     int64_t t_pos, t_neg, t_idle;
     int periodic;
     double f_pos, f_neg, u_limit;
@@ -82,7 +84,7 @@ hipError_t launch_moments(const KParams& P, const float* A, const uint8_t* wall,
 hipError_t launch_state_io(const KParams& P, float* A, const uint8_t* wall, float* f_ext, float* g_ext, int to_ext,
                            hipStream_t st);
 hipError_t launch_diag(const KParams& P, const float* A, const uint8_t* wall, const double* phi, int row0,
-                       int a_min, int64_t step, DiagRow* rows, SampleRec* out, hipStream_t st);
+                       int a_min, int band, int64_t step, DiagRow* rows, SampleRec* out, hipStream_t st);
 
 // (case, strip, first row | rows << 16, first column) tiles of a batch:
 // plain tiles of the wide strips (workgroups of 64 * waves_x lanes) and of

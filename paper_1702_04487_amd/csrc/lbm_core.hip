@@ -1064,7 +1064,7 @@ struct RunSum {
 
 // Thread 0 writes the record to *out and returns it (other threads return
 // an unspecified record).
-__device__ __forceinline__ SampleRec diag_finish(int ny, int row0, int a_min, int64_t step,
+__device__ __forceinline__ SampleRec diag_finish(int ny, int row0, int a_min, int band, int64_t step,
                                                  const DiagRow* __restrict__ rows, SampleRec* __restrict__ out)
 {
     __shared__ double sh[4][DIAG_THREADS];
@@ -1190,15 +1190,32 @@ __device__ __forceinline__ SampleRec diag_finish(int ny, int row0, int a_min, in
     r.largest_count = top.c;
     r.largest_uy = top.u;
     r.largest_top = top.c > 0 ? top.b - 1 : -1;
+    r.largest_bottom = top.c > 0 ? top.a : -1;
+    // head and tail of the largest drop: mean u_y of the ink in its top and
+    // its bottom `band` rows (the drop's rows all hold ink)
+    if (top.c > 0) {
+        double hu = 0.0, tu = 0.0;
+        long long hc = 0, tc = 0;
+        for (int y = max(top.a, top.b - band); y < top.b; ++y) {
+            hu += rows[y].uy;
+            hc += rows[y].count;
+        }
+        for (int y = top.a; y < min(top.b, top.a + band); ++y) {
+            tu += rows[y].uy;
+            tc += rows[y].count;
+        }
+        r.head_uy = hu / (double)hc;
+        r.tail_uy = tu / (double)tc;
+    }
     *out = r;
     return r;
 }
 
-__global__ __launch_bounds__(DIAG_THREADS) void k_diag_finish(int ny, int row0, int a_min, int64_t step,
+__global__ __launch_bounds__(DIAG_THREADS) void k_diag_finish(int ny, int row0, int a_min, int band, int64_t step,
                                                              const DiagRow* __restrict__ rows,
                                                              SampleRec* __restrict__ out)
 {
-    (void)diag_finish(ny, row0, a_min, step, rows, out);
+    (void)diag_finish(ny, row0, a_min, band, step, rows, out);
 }
 
 // ----------------------------------------------------------------- batches
@@ -1294,7 +1311,7 @@ __global__ __launch_bounds__(DIAG_THREADS) void k_batch_diag_finish(const CaseRe
     const int c = blockIdx.x;
     const CaseRec& R = cases[c];
     const int64_t k = n_rec[c];
-    const SampleRec r = diag_finish(R.P.ny, R.row0, R.a_min, *t_dev, R.rows, R.ring + k);
+    const SampleRec r = diag_finish(R.P.ny, R.row0, R.a_min, R.band, *t_dev, R.rows, R.ring + k);
     if (threadIdx.x == 0) {
         n_rec[c] = k + 1;
         if (r.nan_count > 0 || !(r.max_u <= R.u_limit)) active[c] = 0;
@@ -1485,10 +1502,10 @@ hipError_t launch_state_io(const KParams& P, float* A, const uint8_t* wall, floa
 }
 
 hipError_t launch_diag(const KParams& P, const float* A, const uint8_t* wall, const double* phi, int row0,
-                       int a_min, int64_t step, DiagRow* rows, SampleRec* out, hipStream_t st)
+                       int a_min, int band, int64_t step, DiagRow* rows, SampleRec* out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_diag_rows, dim3(P.ny), dim3(DIAG_THREADS), 0, st, P, A, wall, phi, row0, rows);
-    hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(DIAG_THREADS), 0, st, P.ny, row0, a_min, step, rows, out);
+    hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(DIAG_THREADS), 0, st, P.ny, row0, a_min, band, step, rows, out);
     return hipGetLastError();
 }
 

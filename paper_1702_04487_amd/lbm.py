@@ -35,13 +35,14 @@ class IJSample(ctypes.Structure):
                 ("mom_x", ctypes.c_double), ("mom_y", ctypes.c_double), ("max_u", ctypes.c_double),
                 ("nan_count", ctypes.c_int64), ("n_detached", ctypes.c_int64),
                 ("largest_count", ctypes.c_int64), ("largest_uy", ctypes.c_double),
-                ("largest_top", ctypes.c_int64)]
+                ("largest_top", ctypes.c_int64), ("largest_bottom", ctypes.c_int64),
+                ("head_uy", ctypes.c_double), ("tail_uy", ctypes.c_double)]
 
 
 class IJDiag(ctypes.Structure):
     _fields_ = [("step", ctypes.c_int64), ("n_samples", ctypes.c_int64), ("breakup_step", ctypes.c_int64),
                 ("v_drop", ctypes.c_double), ("vol_drop", ctypes.c_int64), ("satellite", ctypes.c_int64),
-                ("unstable_step", ctypes.c_int64), ("last", IJSample)]
+                ("unstable_step", ctypes.c_int64), ("last", IJSample), ("drop_len", ctypes.c_int64)]
 
 
 class LBMError(RuntimeError):

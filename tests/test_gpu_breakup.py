@@ -34,7 +34,7 @@ def test_breakup_time_and_drop_velocity_match_oracle(oracle_mod, gpu_lib):
         if o.t < k:
             o.step(k - o.t)
         d = o.diag(row0)
-        seg = O.segments(d["row_count"], d["row_uy"], row0, 4 * p["width"] ** 2)
+        seg = O.segments(d["row_count"], d["row_uy"], row0, 4 * p["width"] ** 2, O.band_rows(p["width"]))
         seg["step"] = k
         series.append(seg)
     ref = O.breakup_summary(series, ny, p["width"])
@@ -53,3 +53,21 @@ def test_breakup_time_and_drop_velocity_match_oracle(oracle_mod, gpu_lib):
     assert abs(gd["v_drop"] - ref["v_drop"]) <= 0.01 * abs(ref["v_drop"])
     assert abs(gd["vol_drop"] - ref["vol_drop"]) <= 0.01 * ref["vol_drop"]
     assert gd["satellite"] == ref["satellite"]
+    assert gd["drop_len"] == ref["drop_len"] > 0
+
+    # Fig. 3 / Fig. 4 quantities, sample by sample: the drop's extent exactly
+    # and the head and tail velocities within 1e-4 relative plus 1e-5 of the
+    # sample's largest speed (the field tolerance: FP32 velocities carry an
+    # error that scales with the flow, not with the slow drop tip)
+    gs = {s["step"]: s for s in g.samples()}
+    n_cmp = 0
+    for r in series:
+        s = gs[r["step"]]
+        assert (s["n_detached"], s["largest_top"], s["largest_bottom"]) == \
+            (r["n_detached"], r["largest_top"], r["largest_bottom"]), r["step"]
+        if r["n_detached"]:
+            tol = 1e-4 * max(abs(r["head_uy"]), abs(r["tail_uy"])) + 1e-5 * s["max_u"]
+            assert abs(s["head_uy"] - r["head_uy"]) <= tol, (r["step"], s["head_uy"], r["head_uy"])
+            assert abs(s["tail_uy"] - r["tail_uy"]) <= tol, (r["step"], s["tail_uy"], r["tail_uy"])
+            n_cmp += 1
+    assert n_cmp >= 10

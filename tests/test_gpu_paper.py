@@ -35,7 +35,8 @@ def test_paper_trends(gpu_lib):
     preset, see config_paper), the filament breaks up later on a more
     hydrophobic nozzle wall and sooner with a higher surface tension.  The
     absolute times are not pinned (the paper prints no force amplitudes);
-    the signs of the trends are."""
+    the signs of the trends are, and the recoil of the tail after the
+    pinch-off (Fig. 3)."""
     specs = [dict(theta=t) for t in THETAS] + [dict(sigma_mn_per_m=s) for s in SIGMAS]
     cfgs = [W.config_paper(**sp) for sp in specs]
     b = gpu_lib.Batch([dict(c["params"], diag_row0=c["row0"], diag_every=50) for c in cfgs],
@@ -52,6 +53,18 @@ def test_paper_trends(gpu_lib):
         assert d["breakup_step"] > 0, sp
         res.append((u.microseconds(d["breakup_step"]), u.velocity_ms(d["v_drop"])))
         print(sp, f"breakup {res[-1][0]:.1f} us, drop velocity {res[-1][1]:+.3f} m/s")
+    # Fig. 3 at 90 degrees: after the pinch-off the tail recoils towards the
+    # head (tail faster than head over the first 3 us) and the drop contracts
+    k90 = THETAS.index(90.0)
+    sim = b.cases[k90]
+    tb = sim.diagnostics()["breakup_step"]
+    after = [x for x in sim.samples() if x["step"] >= tb and x["largest_count"] > 0]
+    early = [x for x in after if x["step"] <= tb + u.steps(3.0)]
+    recoil = np.mean([x["tail_uy"] - x["head_uy"] for x in early])
+    length = [x["largest_top"] - x["largest_bottom"] + 1 for x in after]
+    print(f"90 deg: tail - head over the first 3 us {u.velocity_ms(recoil):+.3f} m/s; "
+          f"drop length {length[0]} -> {length[-1]} rows over {u.microseconds(after[-1]['step'] - tb):.1f} us")
+    assert recoil > 0 and length[-1] < length[0] - 5
     tb_theta = [r[0] for r in res[:len(THETAS)]]
     tb_sigma = [r[0] for r in res[len(THETAS):]]
     # breakup later with the contact angle (paper: 37 -> 62 us from 30 to 150 deg)

@@ -59,6 +59,24 @@ def test_row_segments_match_component_labelling(seed):
         assert seg["largest_uy"] == pytest.approx(0.01 * max(sizes))
 
 
+def test_segment_head_tail_and_length():
+    """A detached drop of constant width 12 over rows 40..69 whose ink moves
+    at u_y = 0.001 y: the head (top 3 rows) and tail (bottom 3 rows) mean
+    velocities are 0.001 times the mean row of those bands, 0.068 and 0.041."""
+    from oracle.oracle import segments, band_rows
+    row_count = np.zeros(100, dtype=np.int64)
+    row_count[:10] = 5                       # attached: the run that holds row0 = 0
+    row_count[40:70] = 12
+    row_uy = row_count * 0.001 * np.arange(100)
+    band = band_rows(3.0)
+    seg = segments(row_count, row_uy, 0, 20, band)
+    assert band == 3 and seg["n_detached"] == 1
+    assert (seg["largest_bottom"], seg["largest_top"]) == (40, 69)
+    assert seg["head_uy"] == pytest.approx(0.068, rel=1e-12)
+    assert seg["tail_uy"] == pytest.approx(0.041, rel=1e-12)
+    assert band_rows(4.0) == 4 and band_rows(2.5) == 3 and band_rows(0.5) == 1
+
+
 def test_diag_reduction_matches_direct_count(oracle_mod):
     cfg = W.config_nozzle_small()
     s = oracle_mod.OracleSim(cfg["params"], cfg["wall"])
@@ -89,12 +107,12 @@ def test_breakup_summary_on_synthetic_series():
         else:
             n_det = 2 if step >= 5000 else 1
             rec = dict(step=step, n_detached=n_det, largest_count=400,
-                       largest_uy=400 * (0.01 + 1e-6 * step), largest_top=100)
+                       largest_uy=400 * (0.01 + 1e-6 * step), largest_top=100, largest_bottom=60)
         samples.append(rec)
     out = breakup_summary(samples, ny=1000, width=4.0)
     assert out["breakup_step"] == 3000
     vs = [0.01 + 1e-6 * s for s in range(4000, 6001, 50)]
     assert out["v_drop"] == pytest.approx(np.mean(vs), rel=1e-12)
-    assert out["vol_drop"] == 400 and out["satellite"] == 1
+    assert out["vol_drop"] == 400 and out["satellite"] == 1 and out["drop_len"] == 41
     none = breakup_summary(samples[:10], ny=1000, width=4.0)
     assert none["breakup_step"] == -1 and np.isnan(none["v_drop"])
