@@ -16,7 +16,7 @@ constexpr int64_t kSampleCap = 4096;
 // rows per tile of the launch over rows next to solid nodes: short tiles
 // when such rows are few and scattered (many workgroups, little marching),
 // taller ones when a strip has long runs of them (less pipeline overhead)
-constexpr int kGeneralRowsShort = 4, kGeneralRowsTall = 16, kGeneralTallRun = 32;
+constexpr int kGeneralRowsShort = 4, kGeneralRowsTall = 8, kGeneralTallRun = 32;
 
 inline int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
