@@ -150,7 +150,7 @@ def sweep_bench(batched_steps: int = 600, plain_steps: int = 300, plain_every: i
 def surrogate_bench(queries: int = 100000, held: int = 256) -> dict:
     """The sweep surrogate on the stored solver cases: train the 4-member
     ensemble (the library's kernels), calibrate its trust threshold on a 10 %
-    split, judge it on `held` held-out cases, then answer `queries` new
+    split, score it on `held` held-out cases, then answer `queries` new
     query points with the network where it is trusted and the solver
     elsewhere.  Solver cost per case: a timed batched run."""
     import torch

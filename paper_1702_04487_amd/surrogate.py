@@ -1,7 +1,7 @@
 """Sweep surrogate: the lattice Boltzmann solver generates training cases,
 an ensemble of networks is trained on them on the GPU, and queries are
 answered by the network where its members agree and by the solver
-elsewhere (the trust region).  The solver is also the judge of the
+elsewhere (the trust region).  The solver is also the reference for the
 network's error.
 
 Cases follow the paper's sweeps (Figs. 4-7: contact angle, surface tension
@@ -218,7 +218,7 @@ class Surrogate:
 def errors(pred: np.ndarray, y: np.ndarray, v_scale: float = 0.01):
     """Relative errors of breakup step and drop velocity: |dt| / t and
     |dv| / max(|v|, v_scale) (v_scale: a typical drop speed, so that cases
-    without a drop, v = 0, are judged on an absolute scale)."""
+    without a drop, v = 0, are scored on an absolute scale)."""
     et = np.abs(pred[:, 0] - y[:, 0]) / np.maximum(np.abs(y[:, 0]), 1.0)
     ev = np.abs(pred[:, 1] - y[:, 1]) / np.maximum(np.abs(y[:, 1]), v_scale)
     return et, ev

@@ -4,7 +4,7 @@ The ensemble is trained on the GPU by the library's own kernels on the
 stored solver cases (paper_1702_04487_amd/data), its trust threshold is
 calibrated on a 10 % split of them, and 256 held-out cases are answered by
 the network where the members agree and by the solver elsewhere.  The
-solver's stored results judge the answers: those the network gives stay
+solver's stored results score the answers: those the network gives stay
 within 2 % (mean error of breakup step and drop velocity); the rest are
 the solver's own.  Wall times are measured here: the network's prediction,
 and the solver's cost per case from a batched run of held-out cases."""

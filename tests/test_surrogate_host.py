@@ -49,7 +49,7 @@ def test_errors_and_calibration():
     pred = np.array([[10100.0, 0.0202], [20000.0, 0.001], [6000.0, -0.01], [24000.0, 0.0]])
     et, ev = S.errors(pred, y)
     assert np.allclose(et, [0.01, 0.0, 0.2, 0.0])
-    assert np.allclose(ev, [0.01, 0.1, 0.0, 0.0])   # |v| < 0.01 judged against 0.01
+    assert np.allclose(ev, [0.01, 0.1, 0.0, 0.0])   # |v| < 0.01 measured against 0.01
     spread = np.array([0.1, 0.3, 0.5, 0.05])
     # ordered by spread: cases 3, 0, 1, 2; running means of e_t: 0, .005, .0033, .0525;
     # of e_v: 0, .005, .0367 -> the last admissible prefix ends at case 0
