@@ -129,6 +129,7 @@ void fill_kparams(ij_sim* s)
     K.pitch = s->pitch;
     K.bc_open = p.bc_y == IJ_BC_OPEN;
     K.force_rows = (int)std::min<int64_t>(p.force_rows, s->ny);
+    K.diag_row0 = (int)p.diag_row0;
     K.plane = (unsigned)s->plane;
     K.phi_star = s->phi_star;
     K.beta4 = 4.0 * s->beta;
@@ -377,6 +378,7 @@ void ij_host::destroy_sim(ij_sim* s)
     if (s->plain) (void)hipFree(s->plain);
     if (s->gtiles) (void)hipFree(s->gtiles);
     if (s->ptiles) (void)hipFree(s->ptiles);
+    if (s->sample_parts) (void)hipFree(s->sample_parts);
     delete s;
 }
 
@@ -555,16 +557,37 @@ ij_status ij_step(ij_sim* s, int64_t nsteps, void* stream)
     if (nsteps < 0) return fail(s, IJ_ERR_INVALID_ARG, "nsteps < 0");
     if (s->unstable_step >= 0) return fail(s, IJ_ERR_UNSTABLE, "a diagnostics sample failed the stability guard");
     hipStream_t st = (hipStream_t)stream;
+    const int n_sub = (s->nx + 63) / 64;
+    const size_t n_parts = (size_t)n_sub * (size_t)s->ny;
     for (int64_t k = 0; k < nsteps; ++k) {
-        if (s->p.diag_every > 0 && s->t % s->p.diag_every == 0) {
-            ij_status r = record_sample(s, st);
-            if (r != IJ_OK) return r;
+        // a step at a sampling time also takes the sample of its input state
+        // (the collide kernels emit per-piece row partials), instead of a
+        // separate pass over the lattice
+        const bool sample = s->p.diag_every > 0 && s->t % s->p.diag_every == 0;
+        if (sample) {
+            if (s->n_dev_samples >= kSampleCap) {
+                ij_status r = drain_samples(s, st);
+                if (r != IJ_OK) return r;
+            }
+            if (!s->sample_parts && hipMalloc(&s->sample_parts, n_parts * sizeof(ij::DiagRow)) != hipSuccess) {
+                s->sample_parts = nullptr;
+                return fail(s, IJ_ERR_OOM, "sample partials allocation failed");
+            }
+            const hipError_t e = ij::launch_sample_clear(s->sample_parts, n_parts, st);
+            if (e != hipSuccess) return hip_fail(s, e, "sample clear kernel");
         }
         s->K.fb = (float)pulse_value(s->p, s->t);
         hipError_t e = ij::launch_collide_fused(s->K, s->buf[s->cur], s->buf[1 - s->cur], s->wall, s->plain,
                                                 s->ptiles, s->n_ptiles, s->gtiles, s->n_gtiles, s->waves_x,
-                                                s->rows_per_block, st);
+                                                s->rows_per_block, sample ? s->sample_parts : nullptr, st);
         if (e != hipSuccess) return hip_fail(s, e, "collide-stream kernel");
+        if (sample) {
+            const int a_min = (int)std::ceil(4.0 * s->p.width * s->p.width);
+            e = ij::launch_sample_finish(s->sample_parts, n_sub, s->ny, (int)s->p.diag_row0, a_min,
+                                         diag_band(s->p.width), s->t, s->rows, s->samples + s->n_dev_samples, st);
+            if (e != hipSuccess) return hip_fail(s, e, "diagnostics kernels");
+            s->n_dev_samples += 1;
+        }
         s->cur = 1 - s->cur;
         s->t += 1;
     }
@@ -762,7 +785,7 @@ ij_status ij_autotune(ij_sim* s, int32_t trial_steps, void* stream, int32_t* wav
             for (int k = 0; k < n && r == hipSuccess; ++k) {
                 r = ij::launch_collide_fused(s->K, s->buf[cur], s->buf[1 - cur], s->wall, s->plain, s->ptiles,
                                              s->n_ptiles, s->gtiles, s->n_gtiles, s->waves_x, s->rows_per_block,
-                                             st);
+                                             nullptr, st);
                 cur = 1 - cur;
             }
             return r;

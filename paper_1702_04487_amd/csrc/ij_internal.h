@@ -54,6 +54,7 @@ struct ij_sim {
     // tiles that hold the other rows (rebuilt with the wall or the tiling)
     uint8_t* plain = nullptr;
     int4* gtiles = nullptr;            // (strip, block, first column, 0) of the general launch
+    ij::DiagRow* sample_parts = nullptr;   // [ceil(nx/64)][ny] partials of a fused sample (on first use)
     int4* ptiles = nullptr;            // plain tiles that hold a plain row (when listed)
     int n_ptiles = -1;                 // their count; -1: the plain launch covers every tile
     int n_gtiles = 0;

@@ -19,6 +19,7 @@ struct KParams {
     int nx, ny, pitch;
     int bc_open;          // 1: "fully developed" top and bottom rows
     int force_rows;       // body force on fluid nodes with y < force_rows
+    int diag_row0;        // rows y >= diag_row0 count ink in a diagnostics sample
     unsigned plane;       // elements per plane (ny * pitch)
     // double-precision order-parameter constants
     double phi_star, beta4, kappa, gamma, omega_phi, inv_width;
@@ -72,10 +73,19 @@ hipError_t launch_collide_ref(const KParams& P, const float* A, float* B, const 
 // row).  general_tiles lists the (strip, first row, first column, rows)
 // pieces, 64 columns wide and at most kMaxRowsPerBlock rows, that hold the
 // other rows.
+// With sample_parts non-null the step also takes the diagnostics sample of
+// its input state: one DiagRow per 64-column piece and row, [ceil(nx/64)][ny]
+// (pieces without a fluid node are left untouched: clear them first).
 hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, const uint8_t* wall,
                                 const uint8_t* plain_rows, const int4* plain_tiles, int n_plain_tiles,
                                 const int4* general_tiles, int n_general_tiles, int waves_x, int rows_per_block,
-                                hipStream_t st);
+                                DiagRow* sample_parts, hipStream_t st);
+// Sample partials: clear n of them; sum them per row in a fixed order (n_sub
+// pieces per row) into rows[ny] and reduce the rows to the record *out as
+// launch_diag does.
+hipError_t launch_sample_clear(DiagRow* parts, size_t n, hipStream_t st);
+hipError_t launch_sample_finish(const DiagRow* parts, int n_sub, int ny, int row0, int a_min, int band,
+                                int64_t step, DiagRow* rows, SampleRec* out, hipStream_t st);
 hipError_t launch_init(const KParams& P, float* A, const uint8_t* wall, double* phi, const float* src,
                        int from_distance, const float* ux, const float* uy, const int2* ghost_list,
                        int n_ghost, hipStream_t st);

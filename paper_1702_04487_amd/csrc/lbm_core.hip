@@ -515,14 +515,80 @@ __device__ __forceinline__ float from_right(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x130, 0xf, 0xf, false));   // wave_shl:1
 }
 
+// Diagnostics sample terms.  Every path that takes a sample (the separate
+// pass, or a step that samples its input state) reduces the same per-node
+// terms in the same order: a butterfly over the 64 columns of each piece
+// (64-column block of a row), then the pieces of the row in order.  Samples
+// are therefore bit for bit the same whichever path took them.
+struct SampleTerms {
+    double n = 0.0, phi = 0.0, jx = 0.0, jy = 0.0, uy = 0.0;
+    float u = 0.f;
+    int cnt = 0, bad = 0;
+};
+
+__device__ __forceinline__ void sample_node(const Macro& m, bool ink_row, SampleTerms& d)
+{
+    d.n = (double)m.n;
+    d.phi = m.phi;
+    d.jx = (double)m.jx;
+    d.jy = (double)m.jy;
+    const float um = sqrtf(m.ux * m.ux + m.uy * m.uy);
+    if (!isfinite(m.n) || !isfinite(m.phi) || !isfinite(um))
+        d.bad = 1;
+    else
+        d.u = um;
+    if (ink_row && m.phi > 0.0) {
+        d.cnt = 1;
+        d.uy = (double)m.uy;
+    }
+}
+
+// sum over the 64 lanes of the wave (every lane takes part and gets the sum)
+__device__ __forceinline__ DiagRow sample_piece(SampleTerms d)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        d.n += __shfl_xor(d.n, o);
+        d.phi += __shfl_xor(d.phi, o);
+        d.jx += __shfl_xor(d.jx, o);
+        d.jy += __shfl_xor(d.jy, o);
+        d.uy += __shfl_xor(d.uy, o);
+        d.u = fmaxf(d.u, __shfl_xor(d.u, o));
+        d.cnt += __shfl_xor(d.cnt, o);
+        d.bad += __shfl_xor(d.bad, o);
+    }
+    DiagRow r;
+    r.mass_n = d.n;
+    r.mass_phi = d.phi;
+    r.mom_x = d.jx;
+    r.mom_y = d.jy;
+    r.uy = d.uy;
+    r.max_u = (double)d.u;
+    r.count = d.cnt;
+    r.bad = d.bad;
+    return r;
+}
+
+__device__ __forceinline__ void sample_add(DiagRow& r, const DiagRow& q)
+{
+    r.mass_n += q.mass_n;
+    r.mass_phi += q.mass_phi;
+    r.mom_x += q.mom_x;
+    r.mom_y += q.mom_y;
+    r.uy += q.uy;
+    r.max_u = fmax(r.max_u, q.max_u);
+    r.count += q.count;
+    r.bad += q.bad;
+}
+
 // One tile (strip, rows [y0, y1)) of the fused update.  fb is the body force
 // of the step.  Shared by the single-lattice and the batched kernels; it
 // starts with a barrier so that a workgroup may run several tiles in a row.
-template <int NW, bool PLAIN>
+template <int NW, bool PLAIN, bool SAMPLE = false>
 __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const float* __restrict__ A,
                                              float* __restrict__ B, const uint8_t* __restrict__ wall,
                                              const uint8_t* __restrict__ plain_rows, int strip, int x0, int y0,
-                                             int y1)
+                                             int y1, DiagRow* __restrict__ parts = nullptr)
 {
     constexpr int BW = 64 * NW;
     // raw rows rr-3..rr are in use while row rr is processed; the last
@@ -677,6 +743,7 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
             for (int i = 0; i < 9; ++i) fs[i] = 0.f;
 #pragma unroll
             for (int i = 0; i < 5; ++i) h[i] = 0.f;
+            SampleTerms dterm;   // this node's share of a diagnostics sample (SAMPLE only)
             if (own_fluid) {
                 const int rn = (P.bc_open && rc == P.ny - 1) ? rc : rc + 1;
                 const int rs = (P.bc_open && rc == 0) ? rc : rc - 1;
@@ -699,6 +766,7 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
                 Macro mac;
                 node_collide(P, rf[S], gcur, bf16_to_float(s_lo[sc][t]), st, rc < P.force_rows ? fb : 0.f, fs,
                              h, g0h, g0l, mac);
+                if constexpr (SAMPLE) sample_node(mac, rc >= P.diag_row0, dterm);
                 const unsigned bo = boff(x, rc);
                 stf(Bf[0], bo, fs[0]);
                 stf(Bg[0], bo, g0h);
@@ -783,6 +851,12 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
                 stream_shifted<3, true>(sx, h[3], s_out[10][jo + 1], s_g[3][sc][jm], s_g[1][sc][jm],
                                         s_g[3][sc][jm - 1], mask_rel, open_fluid);
             }
+            if constexpr (SAMPLE) {
+                // the wave's 64 columns of row rc are piece x0 / 64 + wave;
+                // a wave past the lattice edge writes nothing
+                const DiagRow r = sample_piece(dterm);
+                if (lane == 0 && t < wv) parts[(size_t)((x0 >> 6) + (t >> 6)) * P.ny + rc] = r;
+            }
         }
         // the distributions of collide row rc + 2 into set S; for rows this
         // launch does not collide the loads go to a row of the block that is
@@ -812,14 +886,14 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
 // and dealt so that runs of consecutive tiles stay on one XCD (workgroups are
 // dealt round-robin over the 8 XCDs, each with its own L2); the other launch
 // takes the (strip, block, first column) pieces of tile_list.
-template <int NW, bool PLAIN>
+template <int NW, bool PLAIN, bool SAMPLE = false>
 __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const float* __restrict__ A,
                                                            float* __restrict__ B,
                                                            const uint8_t* __restrict__ wall,
                                                            const uint8_t* __restrict__ plain_rows,
                                                            const int4* __restrict__ tile_list,
                                                            int rows_per_block, int n_strips,
-                                                           int n_rowblocks)
+                                                           int n_rowblocks, DiagRow* __restrict__ parts)
 {
     if (PLAIN) {
         const int ntiles = n_strips * n_rowblocks;
@@ -828,27 +902,28 @@ __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const floa
         const int rb = tile / n_strips;
         const int strip = tile - rb * n_strips;
         const int y0 = rb * rows_per_block;
-        collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, strip, strip * 64 * NW, y0,
-                                min(P.ny, y0 + rows_per_block));
+        collide_tile<NW, PLAIN, SAMPLE>(P, P.fb, A, B, wall, plain_rows, strip, strip * 64 * NW, y0,
+                                        min(P.ny, y0 + rows_per_block), parts);
     } else {
         const int4 tl = tile_list[blockIdx.x];   // (strip, first row, first column, rows)
-        collide_tile<NW, PLAIN>(P, P.fb, A, B, wall, plain_rows, tl.x, tl.z, tl.y, tl.y + tl.w);
+        collide_tile<NW, PLAIN, SAMPLE>(P, P.fb, A, B, wall, plain_rows, tl.x, tl.z, tl.y, tl.y + tl.w, parts);
     }
 }
 
 // The plain launch over a list of tiles (those that hold a plain row),
 // listed row-block major as (strip, first row, first column, rows): XCD x
 // (workgroup b % 8) takes the x-th contiguous run of the list.
-template <int NW>
+template <int NW, bool SAMPLE = false>
 __global__ __launch_bounds__(64 * NW) void k_collide_listed(KParams P, const float* __restrict__ A,
                                                             float* __restrict__ B,
                                                             const uint8_t* __restrict__ wall,
                                                             const uint8_t* __restrict__ plain_rows,
-                                                            const int4* __restrict__ tile_list)
+                                                            const int4* __restrict__ tile_list,
+                                                            DiagRow* __restrict__ parts)
 {
     const int n = gridDim.x, b = blockIdx.x, xcd = b & 7;
     const int4 tl = tile_list[xcd * (n >> 3) + min(xcd, n & 7) + (b >> 3)];
-    collide_tile<NW, true>(P, P.fb, A, B, wall, plain_rows, tl.x, tl.z, tl.y, tl.y + tl.w);
+    collide_tile<NW, true, SAMPLE>(P, P.fb, A, B, wall, plain_rows, tl.x, tl.z, tl.y, tl.y + tl.w, parts);
 }
 
 // ------------------------------------------------------------ init / moments
@@ -975,68 +1050,49 @@ __global__ void k_state_io(KParams P, float* __restrict__ A, const uint8_t* __re
 // ---------------------------------------------------------------- diagnostics
 //
 // Pass 1: one workgroup per row.  Row ink count (phi > 0, rows >= row0) and
-// summed u_y; partial sums of n, phi, momentum (double), max |u| and the
-// count of non-finite nodes.
+// summed u_y; sums of n, phi, momentum (double), max |u| and the count of
+// non-finite nodes, reduced in the order of every sampling path (sample_piece,
+// sample_add).
 constexpr int DIAG_THREADS = 256;
 
 __device__ __forceinline__ void diag_row(const KParams& P, float fb, const float* __restrict__ A,
                                          const uint8_t* __restrict__ wall, const double* __restrict__ phi,
                                          int row0, DiagRow* __restrict__ rows, int y)
 {
-    double sn = 0, sp = 0, sjx = 0, sjy = 0, suy = 0;
-    float umax = 0.f;
-    int cnt = 0, bad = 0;
-    for (int x = threadIdx.x; x < P.nx; x += DIAG_THREADS) {
-        const unsigned k = (unsigned)y * P.pitch + x;
-        if (wall[k]) continue;
-        float f[9];
-        double st[9], Fx, Fy;
+    // pieces of 64 columns, one per wave at a time, 64 pieces per round; the
+    // pieces of a round are added in order by thread 0
+    constexpr int kRound = 64;
+    __shared__ DiagRow s_piece[kRound];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int n_sub = (P.nx + 63) / 64;
+    DiagRow acc{};
+    for (int k0 = 0; k0 < n_sub; k0 += kRound) {
+        const int k1 = min(n_sub, k0 + kRound);
+        for (int k = k0 + wave; k < k1; k += DIAG_THREADS / 64) {   // uniform over the wave
+            SampleTerms d;
+            const int x = k * 64 + lane;
+            if (x < P.nx) {
+                const unsigned kk = (unsigned)y * P.pitch + x;
+                if (!wall[kk]) {
+                    float f[9];
+                    double st[9], Fx, Fy;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = A[(size_t)i * P.plane + k];
-        load_stencil(P, phi, x, y, st);
-        Macro m;
-        node_macro(P, f, st, y < P.force_rows ? fb : 0.f, m, Fx, Fy);
-        sn += (double)m.n;
-        sp += m.phi;
-        sjx += (double)m.jx;
-        sjy += (double)m.jy;
-        const float um = sqrtf(m.ux * m.ux + m.uy * m.uy);
-        if (!isfinite(m.n) || !isfinite(m.phi) || !isfinite(um))
-            ++bad;
-        else
-            umax = fmaxf(umax, um);
-        if (y >= row0 && m.phi > 0.0) {
-            ++cnt;
-            suy += (double)m.uy;
-        }
-    }
-    __shared__ double sh[6][DIAG_THREADS];
-    __shared__ int shi[2][DIAG_THREADS];
-    const int t = threadIdx.x;
-    sh[0][t] = sn; sh[1][t] = sp; sh[2][t] = sjx; sh[3][t] = sjy; sh[4][t] = suy; sh[5][t] = umax;
-    shi[0][t] = cnt; shi[1][t] = bad;
-    __syncthreads();
-    for (int s = DIAG_THREADS / 2; s > 0; s >>= 1) {
-        if (t < s) {
-            for (int q = 0; q < 5; ++q) sh[q][t] += sh[q][t + s];
-            sh[5][t] = fmax(sh[5][t], sh[5][t + s]);
-            shi[0][t] += shi[0][t + s];
-            shi[1][t] += shi[1][t + s];
+                    for (int i = 0; i < 9; ++i) f[i] = A[(size_t)i * P.plane + kk];
+                    load_stencil(P, phi, x, y, st);
+                    Macro m;
+                    node_macro(P, f, st, y < P.force_rows ? fb : 0.f, m, Fx, Fy);
+                    sample_node(m, y >= row0, d);
+                }
+            }
+            const DiagRow r = sample_piece(d);
+            if (lane == 0) s_piece[k - k0] = r;
         }
         __syncthreads();
+        if (t == 0)
+            for (int k = k0; k < k1; ++k) sample_add(acc, s_piece[k - k0]);
+        __syncthreads();
     }
-    if (t == 0) {
-        DiagRow r;
-        r.mass_n = sh[0][0];
-        r.mass_phi = sh[1][0];
-        r.mom_x = sh[2][0];
-        r.mom_y = sh[3][0];
-        r.uy = sh[4][0];
-        r.max_u = sh[5][0];
-        r.count = shi[0][0];
-        r.bad = shi[1][0];
-        rows[y] = r;
-    }
+    if (t == 0) rows[y] = acc;
 }
 
 __global__ __launch_bounds__(DIAG_THREADS) void k_diag_rows(KParams P, const float* __restrict__ A,
@@ -1339,13 +1395,12 @@ hipError_t launch_collide_ref(const KParams& P, const float* A, float* B, const 
     return hipGetLastError();
 }
 
-hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, const uint8_t* wall,
-                                const uint8_t* plain_rows, const int4* plain_tiles, int n_plain_tiles,
-                                const int4* general_tiles, int n_general_tiles, int waves_x, int rows_per_block,
-                                hipStream_t st)
+template <bool SAMPLE>
+hipError_t launch_collide_fused_t(const KParams& P, const float* A, float* B, const uint8_t* wall,
+                                  const uint8_t* plain_rows, const int4* plain_tiles, int n_plain_tiles,
+                                  const int4* general_tiles, int n_general_tiles, int waves_x, int rows_per_block,
+                                  DiagRow* parts, hipStream_t st)
 {
-    if (rows_per_block < 1 || rows_per_block > kMaxRowsPerBlock || (n_plain_tiles > 0 && !plain_tiles))
-        return hipErrorInvalidValue;
     const int bw = 64 * waves_x;
     const int n_strips = (P.nx + bw - 1) / bw;
     const int n_rb = (P.ny + rows_per_block - 1) / rows_per_block;
@@ -1353,16 +1408,16 @@ hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, cons
         const dim3 grid(n_strips * n_rb);
         switch (waves_x) {
         case 1:
-            hipLaunchKernelGGL((k_collide_fused<1, true>), grid, dim3(64), 0, st, P, A, B, wall, plain_rows,
-                               nullptr, rows_per_block, n_strips, n_rb);
+            hipLaunchKernelGGL((k_collide_fused<1, true, SAMPLE>), grid, dim3(64), 0, st, P, A, B, wall, plain_rows,
+                               nullptr, rows_per_block, n_strips, n_rb, parts);
             break;
         case 2:
-            hipLaunchKernelGGL((k_collide_fused<2, true>), grid, dim3(128), 0, st, P, A, B, wall, plain_rows,
-                               nullptr, rows_per_block, n_strips, n_rb);
+            hipLaunchKernelGGL((k_collide_fused<2, true, SAMPLE>), grid, dim3(128), 0, st, P, A, B, wall,
+                               plain_rows, nullptr, rows_per_block, n_strips, n_rb, parts);
             break;
         case 4:
-            hipLaunchKernelGGL((k_collide_fused<4, true>), grid, dim3(256), 0, st, P, A, B, wall, plain_rows,
-                               nullptr, rows_per_block, n_strips, n_rb);
+            hipLaunchKernelGGL((k_collide_fused<4, true, SAMPLE>), grid, dim3(256), 0, st, P, A, B, wall,
+                               plain_rows, nullptr, rows_per_block, n_strips, n_rb, parts);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1371,13 +1426,16 @@ hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, cons
         const dim3 grid(n_plain_tiles);
         switch (waves_x) {
         case 1:
-            hipLaunchKernelGGL((k_collide_listed<1>), grid, dim3(64), 0, st, P, A, B, wall, plain_rows, plain_tiles);
+            hipLaunchKernelGGL((k_collide_listed<1, SAMPLE>), grid, dim3(64), 0, st, P, A, B, wall, plain_rows,
+                               plain_tiles, parts);
             break;
         case 2:
-            hipLaunchKernelGGL((k_collide_listed<2>), grid, dim3(128), 0, st, P, A, B, wall, plain_rows, plain_tiles);
+            hipLaunchKernelGGL((k_collide_listed<2, SAMPLE>), grid, dim3(128), 0, st, P, A, B, wall, plain_rows,
+                               plain_tiles, parts);
             break;
         case 4:
-            hipLaunchKernelGGL((k_collide_listed<4>), grid, dim3(256), 0, st, P, A, B, wall, plain_rows, plain_tiles);
+            hipLaunchKernelGGL((k_collide_listed<4, SAMPLE>), grid, dim3(256), 0, st, P, A, B, wall, plain_rows,
+                               plain_tiles, parts);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1385,8 +1443,45 @@ hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, cons
     }
     // the general pieces are 64 columns wide: one wave each
     if (n_general_tiles > 0)
-        hipLaunchKernelGGL((k_collide_fused<1, false>), dim3(n_general_tiles), dim3(64), 0, st, P, A, B, wall,
-                           plain_rows, general_tiles, 0, n_strips, n_rb);
+        hipLaunchKernelGGL((k_collide_fused<1, false, SAMPLE>), dim3(n_general_tiles), dim3(64), 0, st, P, A, B,
+                           wall, plain_rows, general_tiles, 0, n_strips, n_rb, parts);
+    return hipGetLastError();
+}
+
+hipError_t launch_collide_fused(const KParams& P, const float* A, float* B, const uint8_t* wall,
+                                const uint8_t* plain_rows, const int4* plain_tiles, int n_plain_tiles,
+                                const int4* general_tiles, int n_general_tiles, int waves_x, int rows_per_block,
+                                DiagRow* sample_parts, hipStream_t st)
+{
+    if (rows_per_block < 1 || rows_per_block > kMaxRowsPerBlock || (n_plain_tiles > 0 && !plain_tiles))
+        return hipErrorInvalidValue;
+    if (sample_parts)
+        return launch_collide_fused_t<true>(P, A, B, wall, plain_rows, plain_tiles, n_plain_tiles, general_tiles,
+                                            n_general_tiles, waves_x, rows_per_block, sample_parts, st);
+    return launch_collide_fused_t<false>(P, A, B, wall, plain_rows, plain_tiles, n_plain_tiles, general_tiles,
+                                         n_general_tiles, waves_x, rows_per_block, nullptr, st);
+}
+
+__global__ void k_sample_clear(DiagRow* __restrict__ parts, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) parts[i] = DiagRow{};
+}
+
+// rows[y] = the partials of row y summed over the pieces in order
+__global__ void k_sample_rows(const DiagRow* __restrict__ parts, int n_sub, int ny, DiagRow* __restrict__ rows)
+{
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= ny) return;
+    DiagRow r{};
+    for (int k = 0; k < n_sub; ++k) sample_add(r, parts[(size_t)k * ny + y]);
+    rows[y] = r;
+}
+
+hipError_t launch_sample_clear(DiagRow* parts, size_t n, hipStream_t st)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sample_clear, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, parts, n);
     return hipGetLastError();
 }
 
@@ -1506,6 +1601,14 @@ hipError_t launch_diag(const KParams& P, const float* A, const uint8_t* wall, co
 {
     hipLaunchKernelGGL(k_diag_rows, dim3(P.ny), dim3(DIAG_THREADS), 0, st, P, A, wall, phi, row0, rows);
     hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(DIAG_THREADS), 0, st, P.ny, row0, a_min, band, step, rows, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_finish(const DiagRow* parts, int n_sub, int ny, int row0, int a_min, int band,
+                                int64_t step, DiagRow* rows, SampleRec* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_sample_rows, dim3((unsigned)((ny + 255) / 256)), dim3(256), 0, st, parts, n_sub, ny, rows);
+    hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(DIAG_THREADS), 0, st, ny, row0, a_min, band, step, rows, out);
     return hipGetLastError();
 }
 

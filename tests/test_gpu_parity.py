@@ -162,6 +162,40 @@ def test_autotune_restores_state(gpu_lib):
         a.autotune(1)
 
 
+@pytest.mark.parametrize("name,tiling", [("nozzle_small", (4, 32)), ("nozzle_ragged", (1, 7)),
+                                         ("walls_block", (2, 16)), ("narrow_open", (4, 64)),
+                                         ("periodic_drops", (4, 5))])
+def test_fused_sample_equals_separate_pass(gpu_lib, name, tiling):
+    """A step at a sampling time takes the sample inside the collide kernels
+    (per-piece row partials); the record equals that of the separate
+    diagnostics pass on the same state bit for bit (both reduce the same
+    per-node terms in the same order), and the sampling steps leave the
+    update bit for bit unchanged."""
+    if name == "nozzle_small":
+        c = W.config_nozzle_small()
+        p, wall, d = dict(c["params"], diag_row0=c["row0"]), c["wall"], c["distance"]
+    else:
+        p, wall, d = _case(name)
+        p = dict(p, diag_row0=p["ny"] // 4)
+    K = 25
+    a = gpu_lib.Sim(dict(p, diag_every=K), wall)
+    b = gpu_lib.Sim(dict(p, diag_every=0), wall)
+    for s in (a, b):
+        s.set_tiling(*tiling)
+        s.init_distance(d)
+    for _ in range(8):
+        b.diag_sample()
+        b.step(K)
+        a.step(K)
+    sa, sb = a.samples(), b.samples()
+    assert len(sa) == len(sb) == 8
+    for x, y in zip(sa, sb):
+        assert repr(x) == repr(y), (x, y)
+    fl = (wall == 0)[None]
+    for u, v in zip(a.state(), b.state()):
+        assert np.array_equal(np.where(fl, _np(u), 0), np.where(fl, _np(v), 0))
+
+
 def test_nozzle_64x256_1000_steps(oracle_mod, gpu_lib):
     """The 64 x 256 nozzle workload, pulse +1e-4 x 200, -5e-5 x 100, idle:
     fields within 1e-5 relative L2 of the FP64 oracle at every checkpoint."""
