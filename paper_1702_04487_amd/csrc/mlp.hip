@@ -314,56 +314,98 @@ __global__ void k_mlp_refresh(MlpDev D)
 
 // ---------------------------------------------------------------- inference
 //
-// grid (query blocks of 64, member): each wave evaluates 16 queries through
-// the three layers with bfloat16 products staged in LDS; out[member][q][0..3]
-// holds the regression outputs in target units and the satellite probability.
+// four consecutive bfloat16 values (8-byte aligned) as one fragment register
+__device__ __forceinline__ bf16x4 frag4(const uint16_t* p) { return *reinterpret_cast<const bf16x4*>(p); }
+
+// grid (query blocks of kInferRows * MT / 64, member): each wave evaluates
+// kInferRows queries (two row tiles) through the three layers with bfloat16
+// products staged in LDS.  Every operand fragment is four consecutive k
+// values (a 64-bit load), and each weight fragment feeds both row tiles.
+// out[member][q][0..3] holds the regression outputs in target units and the
+// satellite probability.
+constexpr int kInferRows = 32;
+constexpr int kInferTiles = kInferRows / 16;
+
 __global__ __launch_bounds__(MT) void k_mlp_infer(MlpDev D, MlpNorm N, const float* __restrict__ X, int n,
                                                   float* __restrict__ out)
 {
     const int mem = blockIdx.y;
     const Member P = member(D, mem);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int q0 = (blockIdx.x * (MT / 64) + wave) * 16;
-    __shared__ uint16_t s_x[MT / 64][16 * 16];
-    __shared__ uint16_t s_a[MT / 64][2][16 * 128];
+    const int i = lane & 15, kq = 4 * (lane >> 4);
+    const int q0 = (blockIdx.x * (MT / 64) + wave) * kInferRows;
+    __shared__ __align__(16) uint16_t s_x[MT / 64][kInferRows * 16];
+    __shared__ __align__(16) uint16_t s_a[MT / 64][2][kInferRows * 128];
     uint16_t* xn = s_x[wave];
     uint16_t* a1 = s_a[wave][0];
     uint16_t* a2 = s_a[wave][1];
-    for (int e = lane; e < 256; e += 64) {
+    for (int e = lane; e < kInferRows * 16; e += 64) {
         const int r = e >> 4, c = e & 15;
         float v = 0.f;
         if (q0 + r < n && c < kMlpIn) v = (X[(size_t)(q0 + r) * kMlpIn + c] - N.x_mean[c]) * N.x_inv_std[c];
         xn[e] = to_bf16(v);
     }
     __syncthreads();
+    // layer 1 (K = 16) and layer 2 (K = 128): column tile by column tile
+    const uint16_t* W1 = P.wb + kMlpW1b;
+    const uint16_t* W2 = P.wb + kMlpW2b;
+    const uint16_t* W3 = P.wb + kMlpW3b;
     for (int nt = 0; nt < 8; ++nt) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mma16(xn, 16, 1, P.wb + kMlpW1b, 1, 16, 0, nt * 16, 16, acc);
+        const bf16x4 b = frag4(W1 + (nt * 16 + i) * 16 + kq);
         const int c = nt * 16 + tile_col();
+        const float bias = P.w[kMlpB1 + c];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a1[tile_row(q) * 128 + c] = to_bf16(gelu(acc[q] + P.w[kMlpB1 + c]));
+        for (int rt = 0; rt < kInferTiles; ++rt) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag4(xn + (rt * 16 + i) * 16 + kq), b, acc, 0, 0, 0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a1[(rt * 16 + tile_row(q)) * 128 + c] = to_bf16(gelu(acc[q] + bias));
+        }
     }
     __syncthreads();
     for (int nt = 0; nt < 8; ++nt) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mma16(a1, 128, 1, P.wb + kMlpW2b, 1, 128, 0, nt * 16, 128, acc);
-        const int c = nt * 16 + tile_col();
+        f32x4 acc[kInferTiles];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a2[tile_row(q) * 128 + c] = to_bf16(gelu(acc[q] + P.w[kMlpB2 + c]));
+        for (int rt = 0; rt < kInferTiles; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < 128; k0 += 16) {
+            const bf16x4 b = frag4(W2 + (nt * 16 + i) * 128 + k0 + kq);
+#pragma unroll
+            for (int rt = 0; rt < kInferTiles; ++rt)
+                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag4(a1 + (rt * 16 + i) * 128 + k0 + kq), b,
+                                                                    acc[rt], 0, 0, 0);
+        }
+        const int c = nt * 16 + tile_col();
+        const float bias = P.w[kMlpB2 + c];
+#pragma unroll
+        for (int rt = 0; rt < kInferTiles; ++rt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) a2[(rt * 16 + tile_row(q)) * 128 + c] = to_bf16(gelu(acc[rt][q] + bias));
     }
     __syncthreads();
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    acc = mma16(a2, 128, 1, P.wb + kMlpW3b, 1, 128, 0, 0, 128, acc);
+    // layer 3: one column tile (the four outputs and padding)
+    f32x4 acc[kInferTiles];
+#pragma unroll
+    for (int rt = 0; rt < kInferTiles; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < 128; k0 += 16) {
+        const bf16x4 b = frag4(W3 + i * 128 + k0 + kq);
+#pragma unroll
+        for (int rt = 0; rt < kInferTiles; ++rt)
+            acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag4(a2 + (rt * 16 + i) * 128 + k0 + kq), b, acc[rt],
+                                                                0, 0, 0);
+    }
     const int c = tile_col();
     if (c < kMlpOut) {
+        const float bias = P.w[kMlpB3 + c];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int r = q0 + tile_row(q);
-            if (r >= n) continue;
-            const float o = acc[q] + P.w[kMlpB3 + c];
-            out[((size_t)mem * n + r) * kMlpOut + c] =
-                c < kMlpReg ? o * N.y_std[c] + N.y_mean[c] : 1.0f / (1.0f + expf(-o));
-        }
+        for (int rt = 0; rt < kInferTiles; ++rt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = q0 + rt * 16 + tile_row(q);
+                if (r >= n) continue;
+                const float o = acc[rt][q] + bias;
+                out[((size_t)mem * n + r) * kMlpOut + c] =
+                    c < kMlpReg ? o * N.y_std[c] + N.y_mean[c] : 1.0f / (1.0f + expf(-o));
+            }
     }
 }
 
@@ -407,7 +449,8 @@ hipError_t mlp_launch_infer(const MlpDev& D, const MlpNorm& N, const float* X, i
                             float* spread, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    const int blocks = (n + 63) / 64;
+    const int per_block = kInferRows * (MT / 64);
+    const int blocks = (n + per_block - 1) / per_block;
     hipLaunchKernelGGL(k_mlp_infer, dim3(blocks, D.n_members), dim3(MT), 0, st, D, N, X, n, members);
     if (mean && spread)
         hipLaunchKernelGGL(k_mlp_reduce, dim3((n * kMlpOut + 255) / 256), dim3(256), 0, st, members, D.n_members, n,
