@@ -73,10 +73,27 @@ def cpu_baseline(cfg, rows: int = 8192, steps: int = 100) -> dict:
     dt = time.perf_counter() - t0
     nodes = p["nx"] * rows
     sim.close()
-    return {"value": round(nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": O.max_threads(),
+    cores = O.max_threads()
+    # the same oracle on one thread, over a smaller band
+    rows1, steps1 = 512, 10
+    O.set_threads(1)
+    try:
+        p1 = dict(cfg["params"], ny=rows1)
+        s1 = O.OracleSim(p1, np.ascontiguousarray(cfg["wall"][:rows1]))
+        s1.init_distance(np.ascontiguousarray(cfg["distance"][:rows1]))
+        s1.step(1)
+        t0 = time.perf_counter()
+        s1.step(steps1)
+        dt1 = time.perf_counter() - t0
+        s1.close()
+    finally:
+        O.set_threads(cores)
+    return {"value": round(nodes * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": cores,
             "kind": "oracle",
             "sample": f"{p['nx']}x{rows} band (rows 0-{rows - 1}) of the same disc field, periodic, "
-                      f"{steps} steps after 1 warm-up, FP64"}
+                      f"{steps} steps after 1 warm-up, FP64",
+            "one_thread": {"value": round(p["nx"] * rows1 * steps1 / dt1 / 1e6, 3), "unit": "MLUPS",
+                           "sample": f"{p['nx']}x{rows1} band, {steps1} steps after 1 warm-up"}}
 
 
 def copy_ceiling_gbs(mib: int = 1792, reps: int = 5):
