@@ -26,7 +26,8 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
-constexpr int MT = 256;   // threads of the training and inference workgroups
+constexpr int MT = 256;         // threads of the inference and refresh workgroups
+constexpr int MT_TRAIN = 1024;  // threads of the training workgroup
 
 __device__ __forceinline__ uint16_t to_bf16(float f)
 {
@@ -152,11 +153,13 @@ __device__ void mlp_refresh_bf16(const float* w, uint16_t* wb, int t, int nt)
 
 // ----------------------------------------------------------------- training
 //
-// One workgroup per ensemble member runs one minibatch step: the rows are
+// One workgroup of MT_TRAIN threads (16 waves: the phases below are split
+// over waves, and more waves hide the latency of each wave's chain of
+// matrix-core products) per ensemble member runs one minibatch step: the rows are
 // idx[member][step][0..S) of (X, Y), or rows 0..S-1 when idx is null.
 // mode 0: gradients into P.g and an Adam update (step number adam_t);
 // mode 1: gradients only.  loss_out[member] (if set) gets the minibatch loss.
-__global__ __launch_bounds__(MT) void k_mlp_step(MlpDev D, MlpNorm N, const float* __restrict__ X,
+__global__ __launch_bounds__(MT_TRAIN) void k_mlp_step(MlpDev D, MlpNorm N, const float* __restrict__ X,
                                                  const float* __restrict__ Y, int n_rows, const int* __restrict__ idx,
                                                  int step, int steps, int S, float lr, int adam_t, int mode,
                                                  float* __restrict__ loss_out)
@@ -170,14 +173,14 @@ __global__ __launch_bounds__(MT) void k_mlp_step(MlpDev D, MlpNorm N, const floa
     __shared__ float s_loss;
     __shared__ int s_rows[kMlpMaxBatch];
     if (t == 0) s_loss = 0.f;
-    for (int r = t; r < S16; r += MT) {
+    for (int r = t; r < S16; r += MT_TRAIN) {
         int src = -1;
         if (r < S) src = idx ? min(max(idx[((size_t)mem * steps + step) * S + r], 0), n_rows - 1) : r;
         s_rows[r] = src;
     }
     __syncthreads();
     // normalised inputs, padded rows and columns zero
-    for (int e = t; e < S16 * 16; e += MT) {
+    for (int e = t; e < S16 * 16; e += MT_TRAIN) {
         const int r = e >> 4, c = e & 15;
         const int src = s_rows[r];
         float v = 0.f;
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(MT) void k_mlp_step(MlpDev D, MlpNorm N, const floa
     // dZ2 = (dO W3) * gelu'(z2)     (B[k][c] = W3[k][c])
     const int wave = t >> 6;
     const int T = S16 / 16;
-    for (int it = wave; it < T * 8; it += MT / 64) {
+    for (int it = wave; it < T * 8; it += MT_TRAIN / 64) {
         const int rt = it >> 3, nt = it & 7;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         acc = mma16(W.dob, 16, 1, P.wb + kMlpW3b, 128, 1, rt * 16, nt * 16, 16, acc);
@@ -232,7 +235,7 @@ __global__ __launch_bounds__(MT) void k_mlp_step(MlpDev D, MlpNorm N, const floa
     }
     __syncthreads();
     // dW3 = dO^T a2 [16][128]; db3 = sum dO
-    for (int it = wave; it < 8; it += MT / 64) {
+    for (int it = wave; it < 8; it += MT_TRAIN / 64) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         acc = mma16(W.dob, 1, 16, W.a2, 128, 1, 0, it * 16, S16, acc);
 #pragma unroll
@@ -244,7 +247,7 @@ __global__ __launch_bounds__(MT) void k_mlp_step(MlpDev D, MlpNorm N, const floa
         P.g[kMlpB3 + t] = s;
     }
     // dW2 = dZ2^T a1 [128][128]; db2 = sum dZ2
-    for (int it = wave; it < 64; it += MT / 64) {
+    for (int it = wave; it < 64; it += MT_TRAIN / 64) {
         const int rt = it >> 3, nt = it & 7;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         acc = mma16(W.dzb, 1, 128, W.a1, 128, 1, rt * 16, nt * 16, S16, acc);
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(MT) void k_mlp_step(MlpDev D, MlpNorm N, const floa
     }
     __syncthreads();
     // dZ1 = (dZ2 W2) * gelu'(z1)     (B[k][c] = W2[k][c])
-    for (int it = wave; it < T * 8; it += MT / 64) {
+    for (int it = wave; it < T * 8; it += MT_TRAIN / 64) {
         const int rt = it >> 3, nt = it & 7;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         acc = mma16(W.dzb, 128, 1, P.wb + kMlpW2b, 128, 1, rt * 16, nt * 16, 128, acc);
@@ -273,7 +276,7 @@ __global__ __launch_bounds__(MT) void k_mlp_step(MlpDev D, MlpNorm N, const floa
     }
     __syncthreads();
     // dW1 = dZ1^T xn [128][16] (columns >= 7 zero); db1 = sum dZ1
-    for (int it = wave; it < 8; it += MT / 64) {
+    for (int it = wave; it < 8; it += MT_TRAIN / 64) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
         acc = mma16(W.dz1b, 1, 128, W.xn, 16, 1, it * 16, 0, S16, acc);
 #pragma unroll
@@ -294,7 +297,7 @@ __global__ __launch_bounds__(MT) void k_mlp_step(MlpDev D, MlpNorm N, const floa
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     const float c1 = (float)(1.0 / (1.0 - pow(0.9, (double)adam_t)));
     const float c2 = (float)(1.0 / (1.0 - pow(0.999, (double)adam_t)));
-    for (int k = t; k < kMlpParams; k += MT) {
+    for (int k = t; k < kMlpParams; k += MT_TRAIN) {
         const float g = P.g[k];
         const float m = b1 * P.m[k] + (1.0f - b1) * g;
         const float v = b2 * P.v[k] + (1.0f - b2) * g * g;
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(MT) void k_mlp_step(MlpDev D, MlpNorm N, const floa
         P.w[k] -= lr * (m * c1) / (sqrtf(v * c2) + eps);
     }
     __syncthreads();
-    mlp_refresh_bf16(P.w, P.wb, t, MT);
+    mlp_refresh_bf16(P.w, P.wb, t, MT_TRAIN);
 }
 
 __global__ void k_mlp_refresh(MlpDev D)
@@ -434,7 +437,7 @@ hipError_t mlp_launch_step(const MlpDev& D, const MlpNorm& N, const float* X, co
                            float* loss_out, hipStream_t st)
 {
     if (S < 1 || S > kMlpMaxBatch || n_rows < 1 || (!idx && S > n_rows)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_mlp_step, dim3(D.n_members), dim3(MT), 0, st, D, N, X, Y, n_rows, idx, step, steps, S, lr,
+    hipLaunchKernelGGL(k_mlp_step, dim3(D.n_members), dim3(MT_TRAIN), 0, st, D, N, X, Y, n_rows, idx, step, steps, S, lr,
                        adam_t, mode, loss_out);
     return hipGetLastError();
 }
