@@ -588,10 +588,10 @@ template <int NW, bool PLAIN, bool SAMPLE = false>
 __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const float* __restrict__ A,
                                              float* __restrict__ B, const uint8_t* __restrict__ wall,
                                              const uint8_t* __restrict__ plain_rows, int strip, int x0, int y0,
-                                             int y1, DiagRow* __restrict__ parts = nullptr)
+                                             int y1, DiagRow* __restrict__ parts = nullptr, bool down = false)
 {
     constexpr int BW = 64 * NW;
-    // raw rows rr-3..rr are in use while row rr is processed; the last
+    // raw rows rr - 3 dir .. rr are in use while row rr is processed; the last
     // reader of a slot finishes before the barrier that ends the row
     constexpr int RING = 4;
     __shared__ double s_raw[RING][BW + 4];
@@ -665,16 +665,22 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
         loh = Alo[kh];
     };
 
-    // rows y0-2 .. y1+1 pass through the ring; the count is rounded up to
-    // an even number (the extra iteration collides nothing)
+    // rows y0-2 .. y1+1 pass through the ring, upwards, or downwards when
+    // `down` is set; the count is rounded up to an even number (the extra
+    // iteration collides nothing).  Every ring slot and stencil neighbour is
+    // addressed by absolute row, so the direction changes only the order of
+    // the rows.  Vertically adjacent tiles that walk towards each other read
+    // their shared halo rows at about the same time, from L2.
     const int nk = ((y1 - y0) + 5) & ~1;
+    const int dir = down ? -1 : 1;
+    const int rfirst = down ? y1 + 1 : y0 - 2;
 
-    // iteration kk: raw row rr = y0 - 2 + kk, phi~ row rr - 1, collide row
-    // rc = rr - 2; register set S = kk % 2
+    // iteration kk: raw row rr = rfirst + dir kk, phi~ row rr - dir, collide
+    // row rc = rr - 2 dir; register set S = kk % 2
     auto body = [&](auto Sc, int kk) {
         constexpr int S = decltype(Sc)::value;
-        const int rr = y0 - 2 + kk;
-        const int rc = rr - 2;
+        const int rr = rfirst + dir * kk;
+        const int rc = rr - 2 * dir;
         const int slot = rr & (RING - 1);
 
         // (1) raw row rr into the LDS ring (non-fluid entries zeroed)
@@ -701,12 +707,12 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
         }
         // the raw row two iterations ahead reuses set S (past the last row
         // the block needs, the loads repeat that row: cache hits, unused)
-        fetch_raw(min(rr + 2, y1 + 1), rg[S], rlo[S], rm[S], hg[S], hlo[S], hm[S], ron[S]);
+        fetch_raw(min(max(rr + 2 * dir, y0 - 2), y1 + 1), rg[S], rlo[S], rm[S], hg[S], hlo[S], hm[S], ron[S]);
         __syncthreads();
 
-        // (2) phi~ of row rr-1
+        // (2) phi~ of row rr - dir
         if (kk >= 1) {
-            const int rgw = rr - 1;
+            const int rgw = rr - dir;
             const int sc = rgw & (RING - 1), sn = (rgw + 1) & (RING - 1), ss = (rgw - 1) & (RING - 1);
             auto phit = [&](int j) -> double {
                 const uint8_t m0 = s_m[sc][j];
@@ -734,7 +740,7 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
 
         // (3) collide and stream row rc (the condition is uniform over the
         // workgroup: every lane reaches the barriers below)
-        if (kk >= 4 && rc < y1 && s_mine[rc - y0]) {
+        if (kk >= 4 && rc >= y0 && rc < y1 && s_mine[rc - y0]) {
             const int jm = t + 2, jo = t + 1;
             const int sc = rc & (RING - 1), sn = (rc + 1) & (RING - 1), ss = (rc - 1) & (RING - 1);
             const bool own_fluid = active && s_m[sc][jm] == 0;
@@ -858,23 +864,23 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
                 if (lane == 0 && t < wv) parts[(size_t)((x0 >> 6) + (t >> 6)) * P.ny + rc] = r;
             }
         }
-        // the distributions of collide row rc + 2 into set S; for rows this
+        // the distributions of collide row rc + 2 dir into set S; for rows this
         // launch does not collide the loads go to a row of the block that is
         // (or is about to be) in the cache, and are unused
         {
-            const int rf2 = rc + 2;
+            const int rf2 = rc + 2 * dir;
             const int rcl = min(max(rf2, y0), y1 - 1);
             const unsigned bo = boff(xc, rcl);
 #pragma unroll
             for (int i = 0; i < 9; ++i) rf[S][i] = ldf(Af[i], bo);
         }
-        if (NW > 1) __syncthreads();   // the ring slot of row rr - 3 is reused next
+        if (NW > 1) __syncthreads();   // the ring slot of row rr - 3 dir is reused next
     };
 
 #pragma unroll
     for (int i = 0; i < 9; ++i) rf[0][i] = rf[1][i] = 0.f;
-    fetch_raw(y0 - 2, rg[0], rlo[0], rm[0], hg[0], hlo[0], hm[0], ron[0]);
-    fetch_raw(y0 - 1, rg[1], rlo[1], rm[1], hg[1], hlo[1], hm[1], ron[1]);
+    fetch_raw(rfirst, rg[0], rlo[0], rm[0], hg[0], hlo[0], hm[0], ron[0]);
+    fetch_raw(rfirst + dir, rg[1], rlo[1], rm[1], hg[1], hlo[1], hm[1], ron[1]);
     __syncthreads();   // s_mine
     for (int kk = 0; kk < nk; kk += 2) {
         body(std::integral_constant<int, 0>{}, kk);
@@ -902,8 +908,9 @@ __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const floa
         const int rb = tile / n_strips;
         const int strip = tile - rb * n_strips;
         const int y0 = rb * rows_per_block;
+        // odd row blocks walk down, towards the block above them
         collide_tile<NW, PLAIN, SAMPLE>(P, P.fb, A, B, wall, plain_rows, strip, strip * 64 * NW, y0,
-                                        min(P.ny, y0 + rows_per_block), parts);
+                                        min(P.ny, y0 + rows_per_block), parts, (rb & 1) != 0);
     } else {
         const int4 tl = tile_list[blockIdx.x];   // (strip, first row, first column, rows)
         collide_tile<NW, PLAIN, SAMPLE>(P, P.fb, A, B, wall, plain_rows, tl.x, tl.z, tl.y, tl.y + tl.w, parts);
@@ -912,18 +919,20 @@ __global__ __launch_bounds__(64 * NW) void k_collide_fused(KParams P, const floa
 
 // The plain launch over a list of tiles (those that hold a plain row),
 // listed row-block major as (strip, first row, first column, rows): XCD x
-// (workgroup b % 8) takes the x-th contiguous run of the list.
+// (workgroup b % 8) takes the x-th contiguous run of the list.  As in the
+// full-grid launch, odd row blocks walk down.
 template <int NW, bool SAMPLE = false>
 __global__ __launch_bounds__(64 * NW) void k_collide_listed(KParams P, const float* __restrict__ A,
                                                             float* __restrict__ B,
                                                             const uint8_t* __restrict__ wall,
                                                             const uint8_t* __restrict__ plain_rows,
                                                             const int4* __restrict__ tile_list,
-                                                            DiagRow* __restrict__ parts)
+                                                            int rows_per_block, DiagRow* __restrict__ parts)
 {
     const int n = gridDim.x, b = blockIdx.x, xcd = b & 7;
     const int4 tl = tile_list[xcd * (n >> 3) + min(xcd, n & 7) + (b >> 3)];
-    collide_tile<NW, true, SAMPLE>(P, P.fb, A, B, wall, plain_rows, tl.x, tl.z, tl.y, tl.y + tl.w, parts);
+    collide_tile<NW, true, SAMPLE>(P, P.fb, A, B, wall, plain_rows, tl.x, tl.z, tl.y, tl.y + tl.w, parts,
+                                   ((tl.y / rows_per_block) & 1) != 0);
 }
 
 // ------------------------------------------------------------ init / moments
@@ -1427,15 +1436,15 @@ hipError_t launch_collide_fused_t(const KParams& P, const float* A, float* B, co
         switch (waves_x) {
         case 1:
             hipLaunchKernelGGL((k_collide_listed<1, SAMPLE>), grid, dim3(64), 0, st, P, A, B, wall, plain_rows,
-                               plain_tiles, parts);
+                               plain_tiles, rows_per_block, parts);
             break;
         case 2:
             hipLaunchKernelGGL((k_collide_listed<2, SAMPLE>), grid, dim3(128), 0, st, P, A, B, wall, plain_rows,
-                               plain_tiles, parts);
+                               plain_tiles, rows_per_block, parts);
             break;
         case 4:
             hipLaunchKernelGGL((k_collide_listed<4, SAMPLE>), grid, dim3(256), 0, st, P, A, B, wall, plain_rows,
-                               plain_tiles, parts);
+                               plain_tiles, rows_per_block, parts);
             break;
         default:
             return hipErrorInvalidValue;
