@@ -22,6 +22,14 @@ def oracle_mod():
 
 
 @pytest.fixture(scope="session")
+def oracle3d_mod():
+    from oracle import oracle3d as O3
+    if not os.path.exists(O3.LIB) or os.path.getmtime(O3.LIB) < os.path.getmtime(O3.SRC):
+        O3.build()
+    return O3
+
+
+@pytest.fixture(scope="session")
 def gpu_lib():
     """The HIP library through its Python binding; the test is an error (not a
     silent skip) when the GPU or the library is missing."""

@@ -401,3 +401,80 @@ def minibatch_order(seed: int, n: int, steps: int, batch: int) -> np.ndarray:
     """[steps, batch] sample indices drawn uniformly from [0, n) (int32)."""
     u = uniform_array(seed, steps * batch)
     return np.minimum((u * n).astype(np.int64), n - 1).astype(np.int32).reshape(steps, batch)
+
+
+# ------------------------------------------------- three-dimensional inputs
+# Arrays are indexed [y, z, x]: x periodic (width), y the jet direction,
+# z periodic (depth).
+def round_nozzle_wall3d(nx: int, ny: int, nz: int, radius: float, length: int,
+                        xc: float = None, zc: float = None) -> np.ndarray:
+    """Solid plate y < length with a round bore of the given radius about
+    (xc, zc) (default: the centre of the x-z section).  Solid nodes next to the
+    bore in the x-z plane (8 neighbours) are the inner wall (class 1); the rest
+    of the plate, including its top face, is the outer plate (class 2)."""
+    xc = (nx - 1) / 2.0 if xc is None else xc
+    zc = (nz - 1) / 2.0 if zc is None else zc
+    z, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    bore = (x - xc) ** 2 + (z - zc) ** 2 < radius * radius
+    near = np.zeros_like(bore)
+    for dz in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            near |= np.roll(np.roll(bore, dz, axis=0), dx, axis=1)
+    sec = np.where(bore, FLUID, np.where(near, WALL_INNER, WALL_OUTER)).astype(np.uint8)
+    wall = np.zeros((ny, nz, nx), dtype=np.uint8)
+    if length > 0:
+        wall[:length] = sec[None]
+    return wall
+
+
+def meniscus_distance3d(nx: int, ny: int, nz: int, length: int) -> np.ndarray:
+    """Ink below the nozzle exit, flat meniscus half a node above the last
+    nozzle row; positive inside the ink."""
+    y = np.arange(ny, dtype=np.float64)[:, None, None]
+    return np.broadcast_to(length - 0.5 - y, (ny, nz, nx)).copy()
+
+
+def spheres_distance3d(nx: int, ny: int, nz: int, spheres: Sequence[Tuple[float, float, float, float]],
+                       far: float = -1.0e3) -> np.ndarray:
+    """Signed distance to a union of spheres (cx, cy, cz, r) in a box periodic
+    in all three directions (max over spheres of r - |x - c|, nearest image)."""
+    y, z, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nz, dtype=np.float64),
+                          np.arange(nx, dtype=np.float64), indexing="ij")
+    d = np.full((ny, nz, nx), far, dtype=np.float64)
+    for (cx, cy, cz, r) in spheres:
+        dx = np.abs(x - cx)
+        dx = np.minimum(dx, nx - dx)
+        dy = np.abs(y - cy)
+        dy = np.minimum(dy, ny - dy)
+        dz = np.abs(z - cz)
+        dz = np.minimum(dz, nz - dz)
+        d = np.maximum(d, r - np.sqrt(dx * dx + dy * dy + dz * dz))
+    return d
+
+
+def base_params3d(nx: int, ny: int, nz: int, **kw) -> dict:
+    p = base_params(nx, ny, **kw)
+    p["nz"] = nz
+    return p
+
+
+def config_round_nozzle_small() -> dict:
+    """32 x 96 x 32 round nozzle (FP64 parity workload): bore radius 8 and
+    length 32, density 1.0/0.1, tau 0.8 ink / 1.0 ambient, contact angles 60
+    (bore) and 120 (plate), pulse +1e-3 for 60 steps, -5e-4 for 30, idle."""
+    nx, ny, nz, r, L = 32, 96, 32, 8.0, 32
+    p = base_params3d(nx, ny, nz, force_rows=L, t_pos=60, t_neg=30, t_idle=1000, f_pos=1e-3, f_neg=5e-4,
+                      tau_ink=0.8, theta_inner=60.0, theta_outer=120.0)
+    return dict(name="round_nozzle_32x96x32", params=p, wall=round_nozzle_wall3d(nx, ny, nz, r, L),
+                distance=meniscus_distance3d(nx, ny, nz, L), row0=L, steps=200, nozzle=(r, L))
+
+
+def config_round_nozzle(nx: int = 256, ny: int = 512, nz: int = 256) -> dict:
+    """256 x 512 x 256 round nozzle (33.6 M nodes, the node count of the
+    2048 x 16384 droplet field): bore radius 32 and length 128, the small
+    case's fluid and pulse with durations scaled to the larger bore."""
+    r, L = 32.0, 128
+    p = base_params3d(nx, ny, nz, force_rows=L, t_pos=2000, t_neg=1000, t_idle=57000, f_pos=2e-4,
+                      f_neg=1e-4, tau_ink=0.8, theta_inner=60.0, theta_outer=120.0)
+    return dict(name=f"round_nozzle_{nx}x{ny}x{nz}", params=p, wall=round_nozzle_wall3d(nx, ny, nz, r, L),
+                distance=meniscus_distance3d(nx, ny, nz, L), row0=L, steps=60000, nozzle=(r, L))
