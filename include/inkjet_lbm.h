@@ -356,6 +356,87 @@ ij_status ij_mlp_train(ij_mlp *m, const float *x_dev, const float *y_dev, int32_
 ij_status ij_mlp_predict(ij_mlp *m, const float *x_dev, int64_t n, float *mean_dev, float *spread_dev,
                          float *members_dev, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Three-dimensional lattice (round nozzles).
+ *
+ * The update of the two-dimensional entry points written on D3Q19 (f) and
+ * D3Q7 (g): Methods, Eqs. 1-10, with the pulse of Fig. 1 and the wetting
+ * walls of "Reproducing the experiment".  Every closure and boundary rule
+ * is the two-dimensional one carried to three dimensions:
+ *   f equilibrium w_i [A_i + n (3 c.u + 9/2 (c.u)^2 - 3/2 u^2)], A_i = 3p off
+ *   rest, A_0 = 3n - 6p at rest, p = n/3 + phi mu (Eqs. 5-6);
+ *   g equilibrium g_0 = phi - 3 Gamma mu, g_i = Gamma mu/2 + phi c_i.u/(2q)
+ *   (Eqs. 9-10); gradient and Laplacian over the 18 D3Q19 neighbours; the
+ *   wetting ghost averages the fluid axis neighbours (else the 12 edge
+ *   neighbours).  Summed along one axis D3Q19 has the D2Q9 weights, so a
+ *   state that does not vary along z evolves as the two-dimensional update.
+ *
+ * Axes: x in [0,nx) periodic (width), y in [0,ny) the jet direction
+ * (periodic or open rows), z in [0,nz) periodic (depth).  Every field array
+ * the caller passes or receives is [ny][nz][nx] (index (y*nz + z)*nx + x).
+ * Velocities: 0 rest; 1..6 = +x, +y, -x, -y, +z, -z (D3Q7 = 0..6);
+ * 7..10 = (1,1,0) (-1,1,0) (-1,-1,0) (1,-1,0); 11..14 = (1,0,1) (-1,0,1)
+ * (-1,0,-1) (1,0,-1); 15..18 = (0,1,1) (0,-1,1) (0,-1,-1) (0,1,-1).
+ * Distribution arrays exchanged with the caller are [19][ny][nz][nx] (f)
+ * and [7][ny][nz][nx] (g).  Error handling, streams and ownership follow the
+ * conventions at the top of this file.
+ * ------------------------------------------------------------------------ */
+typedef struct ij3_params {
+    int64_t nx, ny, nz;        /* lattice size, each >= 3 */
+    int64_t bc_y;              /* IJ_BC_PERIODIC or IJ_BC_OPEN (rows y = 0 and ny-1) */
+    int64_t force_rows;        /* body force along +y on fluid nodes with y < force_rows */
+    int64_t t_pos, t_neg, t_idle, periodic_pulse; /* pulse of Fig. 1, in steps */
+    double rho_ink, rho_amb, sigma, width, gamma;
+    double tau_ink, tau_amb, tau_phi;
+    double theta_inner, theta_outer; /* contact angles of wall classes 1 and 2 (degrees) */
+    double f_pos, f_neg;
+} ij3_params;
+
+typedef struct ij3_sim ij3_sim;
+
+/* Validate *p and allocate, on the current device, two distribution buffers
+ * (19 + 7 float planes of ny*nz rows, row pitch nx rounded up to 64), the
+ * phi field (double) and the wall mask from `wall` (host, [ny][nz][nx]
+ * bytes, IJ_FLUID / IJ_WALL_INNER / IJ_WALL_OUTER; NULL: all fluid).  With
+ * open rows, a fluid node of row 0 (ny-1) must have fluid directly above
+ * (below) it.  *out is NULL on failure; ij3_last_error(NULL) says why. */
+ij_status ij3_create(const ij3_params *p, const uint8_t *wall, ij3_sim **out);
+void ij3_destroy(ij3_sim *s);
+const char *ij3_last_error(const ij3_sim *s);
+
+/* Initial state at t = 0: phi from src (device float [ny][nz][nx]; with
+ * from_distance != 0 src is a signed distance d to the ink, positive inside,
+ * and phi = phi* tanh(2d/W)); n = n0; velocity from ux, uy, uz (device, NULL
+ * = 0); f = f_eq and g = g_eq with mu from phi and its wetting ghosts.
+ * Asynchronous. */
+ij_status ij3_init(ij3_sim *s, const float *src_dev, int32_t from_distance, const float *ux_dev,
+                   const float *uy_dev, const float *uz_dev, void *stream);
+
+/* nsteps time steps (Eqs. 3, 4, 8): phi and its ghosts, then one fused
+ * collide-and-push launch, then the open rows.  Asynchronous. */
+ij_status ij3_step(ij3_sim *s, int64_t nsteps, void *stream);
+int64_t ij3_time(const ij3_sim *s);
+
+/* n, phi, u of the current state into device float arrays [ny][nz][nx]
+ * (NULL = skip; solid nodes read 0).  Asynchronous. */
+ij_status ij3_get_moments(ij3_sim *s, float *n_dev, float *phi_dev, float *ux_dev, float *uy_dev,
+                          float *uz_dev, void *stream);
+
+/* Distributions to / from device float arrays [19][ny][nz][nx] and
+ * [7][ny][nz][nx] (solid nodes read 0 and are not written).  set_state also
+ * sets the step counter.  Asynchronous. */
+ij_status ij3_get_state(ij3_sim *s, float *f_dev, float *g_dev, void *stream);
+ij_status ij3_set_state(ij3_sim *s, const float *f_dev, const float *g_dev, int64_t t, void *stream);
+
+/* Diagnostic sums of the current state (Results: mass, momentum, breakup):
+ * rec (host, 7 doubles) = {sum n, sum phi, sum c_x f, sum c_y f, sum c_z f,
+ * max |u|, fluid nodes with a non-finite n, phi or u}; for each row y
+ * (an x-z slice) with y >= row0, row_count[y] (host int64) = fluid nodes
+ * with phi > 0 and row_uy[y] (host double) = the sum of their u_y (0 below
+ * row0; either pointer may be NULL).  Sums accumulate in double in a fixed
+ * order.  Synchronises the stream. */
+ij_status ij3_sample(ij3_sim *s, int64_t row0, double *rec, int64_t *row_count, double *row_uy, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

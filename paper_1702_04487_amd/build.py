@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libinkjet_lbm.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("lbm_core.hip", "ij_api.cpp", "ij_batch.cpp", "mlp.hip", "ij_mlp.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("lbm_core.hip", "ij_api.cpp", "ij_batch.cpp", "mlp.hip", "ij_mlp.cpp",
+                                          "lbm3d.hip")]
 CALIB = os.path.join(HERE, "bin", "copy_calib")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

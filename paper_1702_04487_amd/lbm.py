@@ -63,7 +63,17 @@ EXPORTS = ["ij_params_default", "ij_create", "ij_destroy", "ij_last_error", "ij_
            "ij_batch_time", "ij_batch_step", "ij_batch_set_graph", "ij_batch_set_tiling", "ij_batch_get_tiling",
            "ij_batch_autotune",
            "ij_mlp_create", "ij_mlp_destroy", "ij_mlp_last_error", "ij_mlp_param_count", "ij_mlp_set_weights",
-           "ij_mlp_get_weights", "ij_mlp_set_scaling", "ij_mlp_gradients", "ij_mlp_train", "ij_mlp_predict"]
+           "ij_mlp_get_weights", "ij_mlp_set_scaling", "ij_mlp_gradients", "ij_mlp_train", "ij_mlp_predict",
+           "ij3_create", "ij3_destroy", "ij3_last_error", "ij3_init", "ij3_step", "ij3_time", "ij3_get_moments",
+           "ij3_get_state", "ij3_set_state", "ij3_sample"]
+
+_INT3 = ["nx", "ny", "nz", "bc_y", "force_rows", "t_pos", "t_neg", "t_idle", "periodic_pulse"]
+_DBL3 = ["rho_ink", "rho_amb", "sigma", "width", "gamma", "tau_ink", "tau_amb", "tau_phi", "theta_inner",
+         "theta_outer", "f_pos", "f_neg"]
+
+
+class IJ3Params(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in _INT3] + [(k, ctypes.c_double) for k in _DBL3]
 
 
 def load(path: str = LIB_PATH):
@@ -123,6 +133,16 @@ def load(path: str = LIB_PATH):
         "ij_mlp_gradients": (st, [vp, vp, vp, i32, vp, vp, vp]),
         "ij_mlp_train": (st, [vp, vp, vp, i32, vp, i32, i32, ctypes.c_float, vp, vp]),
         "ij_mlp_predict": (st, [vp, vp, i64, vp, vp, vp, vp]),
+        "ij3_create": (st, [ctypes.POINTER(IJ3Params), vp, ctypes.POINTER(vp)]),
+        "ij3_destroy": (None, [vp]),
+        "ij3_last_error": (ctypes.c_char_p, [vp]),
+        "ij3_init": (st, [vp, vp, i32, vp, vp, vp, vp]),
+        "ij3_step": (st, [vp, i64, vp]),
+        "ij3_time": (i64, [vp]),
+        "ij3_get_moments": (st, [vp, vp, vp, vp, vp, vp, vp]),
+        "ij3_get_state": (st, [vp, vp, vp, vp]),
+        "ij3_set_state": (st, [vp, vp, vp, i64, vp]),
+        "ij3_sample": (st, [vp, i64, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

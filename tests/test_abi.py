@@ -18,7 +18,7 @@ def _declared():
         if fn.endswith(".h"):
             src = open(os.path.join(ROOT, "include", fn)).read()
             src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-            names |= set(re.findall(r"\b(ij_\w+)\s*\(", src))
+            names |= set(re.findall(r"\b(ij3?_\w+)\s*\(", src))
     return names
 
 

@@ -1,0 +1,247 @@
+"""Parity of the three-dimensional HIP path (ij3_* through the C ABI) with the
+FP64 three-dimensional oracle, on the same seeded inputs.
+
+Tolerances, FP32 against FP64 (as for the two-dimensional path): after one
+step every distribution within 2e-6 of the oracle (values are O(0.5) and a
+node's update is a few dozen FP32 operations at ~6e-8 relative each); over
+many steps relative L2 <= 1e-5 on n, phi, n + phi and the velocity vector
+field.  Diagnostics: sums within their FP32 inputs' rounding; ink counts
+differ only where |phi| is at rounding level."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def _case(name):
+    """Small lattices that span several workgroups and ragged tails in x and z."""
+    if name == "round_nozzle":
+        c = W.config_round_nozzle_small()
+        return c["params"], c["wall"], c["distance"]
+    if name == "blobs_walls_ragged":
+        nx, ny, nz = 70, 24, 7
+        p = W.base_params3d(nx, ny, nz, bc_y=W.BC_PERIODIC, tau_ink=0.7, tau_amb=1.1, tau_phi=0.9, gamma=0.8,
+                            theta_inner=40.0, theta_outer=135.0, force_rows=ny, f_pos=2e-5, t_pos=10 ** 6)
+        wall = np.zeros((ny, nz, nx), np.uint8)
+        wall[0:2] = W.WALL_OUTER
+        wall[8:12, 2:5, 30:41] = W.WALL_INNER
+        d = W.spheres_distance3d(nx, ny, nz, [(20.3, 12.1, 3.0, 6.5), (55.0, 16.0, 4.5, 4.0)])
+        return p, wall, d
+    if name == "narrow_open":
+        nx, ny, nz = 3, 30, 3
+        p = W.base_params3d(nx, ny, nz, bc_y=W.BC_OPEN, force_rows=12, f_pos=1e-4, t_pos=10 ** 6)
+        y = np.arange(ny)[:, None, None].astype(float)
+        return p, np.zeros((ny, nz, nx), np.uint8), np.broadcast_to(12.5 - y, (ny, nz, nx)).copy()
+    raise KeyError(name)
+
+
+CASES = ["round_nozzle", "blobs_walls_ragged", "narrow_open"]
+
+
+def _pair(O3, p, wall, d):
+    from paper_1702_04487_amd import lbm3d
+    o = O3.Oracle3D(p, wall)
+    o.init_distance(d)
+    g = lbm3d.Sim3D(p, wall)
+    g.init_distance(d)
+    return o, g
+
+
+def _compare_state(o, g, tol):
+    fo, go = o.get_state()
+    fg, gg = g.state()
+    fl = (o.wall == 0)[None]
+    df = np.abs(np.where(fl, _np(fg) - fo, 0.0)).max()
+    dg = np.abs(np.where(fl, _np(gg) - go, 0.0)).max()
+    assert df < tol and dg < tol, (df, dg)
+
+
+def _compare_fields(o, g, tol):
+    mo = o.fields()
+    mg = {k: _np(v) for k, v in g.moments().items()}
+    fl = o.wall == 0
+    errs = {k: rel_l2(mg[k][fl], mo[k][fl]) for k in ("n", "phi")}
+    errs["rho"] = rel_l2((mg["n"] + mg["phi"])[fl], (mo["n"] + mo["phi"])[fl])
+    errs["u"] = rel_l2(np.stack([mg[k][fl] for k in ("ux", "uy", "uz")]),
+                       np.stack([mo[k][fl] for k in ("ux", "uy", "uz")]))
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, errs
+    return errs
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_initial_state_matches_oracle(oracle3d_mod, gpu_lib, name):
+    print("3-D initial state", name, flush=True)
+    o, g = _pair(oracle3d_mod, *_case(name))
+    _compare_state(o, g, 2e-6)
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_one_step_and_twenty_steps(oracle3d_mod, gpu_lib, name):
+    print("3-D 1 + 19 steps", name, flush=True)
+    o, g = _pair(oracle3d_mod, *_case(name))
+    o.step(1)
+    g.step(1)
+    _compare_state(o, g, 2e-6)
+    o.step(19)
+    g.step(19)
+    assert g.t == o.t == 20
+    _compare_fields(o, g, 1e-5)
+
+
+def test_round_nozzle_pulse(oracle3d_mod, gpu_lib):
+    """The 32 x 96 x 32 round nozzle through its +/- pulse (60 + 30 steps)
+    and after: fields within 1e-5 relative L2 at every checkpoint."""
+    print("3-D round nozzle 200 steps", flush=True)
+    c = W.config_round_nozzle_small()
+    o, g = _pair(oracle3d_mod, c["params"], c["wall"], c["distance"])
+    worst = {}
+    for t in (60, 90, 200):
+        o.step(t - o.t)
+        g.step(t - g.t)
+        for k, v in _compare_fields(o, g, 1e-5).items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    print("worst relative L2:", worst)
+    assert np.max(np.abs(o.fields()["uy"])) > 1e-3   # the pulse moved the ink
+
+
+def test_diagnostics_match_oracle(oracle3d_mod, gpu_lib):
+    print("3-D diagnostics", flush=True)
+    c = W.config_round_nozzle_small()
+    o, g = _pair(oracle3d_mod, c["params"], c["wall"], c["distance"])
+    row0 = c["row0"]
+    for t in (0, 70, 150):
+        o.step(t - o.t)
+        g.step(t - g.t)
+        s = g.sample(row0)
+        od = o.diag(row0)
+        assert s["mass_n"] == pytest.approx(od["mass_n"], rel=1e-6)
+        assert s["mass_phi"] == pytest.approx(od["mass_phi"], rel=1e-5, abs=1e-6 * od["mass_n"])
+        scale = np.abs(od["mom"]).sum()
+        assert np.all(np.abs(s["mom"] - od["mom"]) <= 1e-5 * scale + 1e-9), (s["mom"], od["mom"])
+        assert s["max_u"] == pytest.approx(od["max_u"], rel=1e-4, abs=1e-7)
+        assert s["nan_count"] == 0
+        phi = o.fields()["phi"]
+        amb = ((np.abs(phi) < 1e-5) & (c["wall"] == 0)).sum(axis=(1, 2))
+        assert np.all(np.abs(s["row_count"] - od["row_count"]) <= amb)
+        assert np.all(s["row_count"][:row0] == 0)
+        scale_u = np.abs(od["row_uy"]).max() + 1e-12
+        assert np.all(np.abs(s["row_uy"] - od["row_uy"]) <= 1e-4 * scale_u + 1e-7 * od["row_count"])
+
+
+def test_closed_box_conserves_mass(gpu_lib):
+    """Periodic box with a floor and a block: sum n and sum phi stay fixed to
+    float rounding over 400 steps."""
+    print("3-D closed box 400 steps", flush=True)
+    from paper_1702_04487_amd import lbm3d
+    p, wall, d = _case("blobs_walls_ragged")
+    g = lbm3d.Sim3D(p, wall)
+    g.init_distance(d)
+    a = g.sample()
+    g.step(400)
+    b = g.sample()
+    assert abs(b["mass_n"] - a["mass_n"]) < 2e-6 * a["mass_n"]
+    assert abs(b["mass_phi"] - a["mass_phi"]) < 2e-6 * a["mass_n"]
+    assert b["max_u"] > 1e-4 and b["nan_count"] == 0
+
+
+def test_state_round_trip_and_restart(oracle3d_mod, gpu_lib):
+    """A state written through ij3_set_state reads back, and stepping it
+    matches the oracle stepped from the same state."""
+    print("3-D set_state / restart", flush=True)
+    from paper_1702_04487_amd import lbm3d
+    p, wall, d = _case("round_nozzle")
+    o = oracle3d_mod.Oracle3D(p, wall)
+    o.init_distance(d)
+    o.step(30)
+    fo, go = o.get_state()
+    g = lbm3d.Sim3D(p, wall)
+    g.set_state(fo, go, t=30)
+    fg, gg = g.state()
+    fl = (wall == 0)[None]
+    assert np.abs(np.where(fl, _np(fg) - fo, 0)).max() < 1e-7
+    assert np.abs(np.where(fl, _np(gg) - go, 0)).max() < 1e-7
+    o.step(5)
+    g.step(5)
+    assert g.t == 35
+    _compare_state(o, g, 2e-6)
+
+
+def test_errors(gpu_lib):
+    from paper_1702_04487_amd import lbm, lbm3d
+    p, wall, d = _case("narrow_open")
+    g = lbm3d.Sim3D(p, wall)
+    with pytest.raises(lbm.LBMError) as e:
+        g.step(1)
+    assert e.value.code == lbm.IJ_ERR_STATE
+    bad = wall.copy()
+    bad[1] = W.WALL_OUTER        # an open row's fluid node with a wall inside it
+    with pytest.raises(lbm.LBMError) as e:
+        lbm3d.Sim3D(p, bad)
+    assert e.value.code == lbm.IJ_ERR_INVALID_ARG
+
+
+def _window_compare(O3, p_full, wall, d, g_mom, y0, z0, x0, h, dz, dx, k, bc_y):
+    """The oracle on a window of the full lattice: after k steps every node
+    farther than 2k + 2 from a window edge that is not a true boundary
+    depends only on initial data inside the window (the stencil plus
+    streaming reach is two nodes per step), so there it equals the full run."""
+    ny, nz, nx = wall.shape
+    ys, zs, xs = np.arange(y0, y0 + h) % ny, np.arange(z0, z0 + dz) % nz, np.arange(x0, x0 + dx) % nx
+    pw = dict(p_full, nx=dx, ny=h, nz=dz, bc_y=bc_y)
+    pw["force_rows"] = int(np.clip(p_full["force_rows"] - y0, 0, h))
+    ow = O3.Oracle3D(pw, wall[np.ix_(ys, zs, xs)])
+    ow.init_distance(d[np.ix_(ys, zs, xs)])
+    ow.step(k)
+    mo = ow.fields()
+    m = 2 * k + 2
+    open_y = bc_y == W.BC_OPEN
+    r0 = 0 if (open_y and y0 == 0) else m
+    r1 = h if (open_y and y0 + h == ny) else h - m
+    inner = (slice(r0, r1), slice(m, dz - m), slice(m, dx - m))
+    fl = wall[np.ix_(ys, zs, xs)][inner] == 0
+    out = {}
+    for key in ("n", "phi", "ux", "uy", "uz"):
+        out[key] = np.abs(g_mom[key][np.ix_(ys, zs, xs)][inner][fl] - mo[key][inner][fl]).max()
+    return out
+
+
+def test_full_size_round_nozzle_sampled(oracle3d_mod, gpu_lib):
+    """256 x 512 x 256 round nozzle at full size (the benchmarked launch):
+    windows computed by the oracle (the bore's open bottom, the bore wall,
+    the nozzle exit with the meniscus, the chamber and the open top) agree
+    with the GPU run."""
+    print("3-D full size 256x512x256", flush=True)
+    from paper_1702_04487_amd import lbm3d
+    c = W.config_round_nozzle()
+    p, wall, d = c["params"], c["wall"], c["distance"]
+    g = lbm3d.Sim3D(p, wall)
+    g.init_distance(d)
+    k = 5
+    g.step(k)
+    gm = {key: _np(v) for key, v in g.moments().items()}
+    del g
+    ny, nz, nx = wall.shape
+    r, L = c["nozzle"]
+    cx = (nx - 1) / 2
+    spots = [(0, int(cx), int(cx - r), W.BC_OPEN),                  # open bottom row, bore wall
+             (L - 18, int(cx + 10), int(cx + r - 4), W.BC_PERIODIC),  # nozzle exit, meniscus on the rim
+             (300, 40, 200, W.BC_PERIODIC),                          # chamber
+             (ny - 36, 100, 7, W.BC_OPEN)]                           # open top row
+    for (yc, zc, xc, bc) in spots:
+        y0 = 0 if bc == W.BC_OPEN and yc == 0 else yc
+        errs = _window_compare(oracle3d_mod, p, wall, d, gm, y0, zc - 18, xc - 18, 36, 36, 36, k, bc)
+        print("window", (yc, zc, xc), errs, flush=True)
+        assert errs["n"] < 2e-6 and errs["phi"] < 2e-6, errs
+        assert max(errs["ux"], errs["uy"], errs["uz"]) < 1e-7, errs
