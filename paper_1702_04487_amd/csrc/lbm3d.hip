@@ -134,15 +134,33 @@ __device__ __forceinline__ Phi3 phi_fields(const K3& P, const double* __restrict
     return r;
 }
 
-// collide every fluid node and push its populations (Eqs. 3, 4, 8)
+// collide every fluid node and push its populations (Eqs. 3, 4, 8).
+// The workgroup first stages phi and the wall bytes of its tile and a
+// one-node halo (three y-slices) in LDS: the stencil and the destination
+// checks then read LDS instead of issuing 36 scattered loads per node.
+constexpr int HX = BX + 2, HZ = BZ + 2, HN = 3 * HZ * HX;
+constexpr uint8_t kBeyond = 255;   // LDS wall byte of a node beyond an open row
 __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restrict__ A, float* __restrict__ B,
                                                      const uint8_t* __restrict__ wall,
                                                      const double* __restrict__ phi, float fb)
 {
-    const int x = blockIdx.x * BX + threadIdx.x, z = blockIdx.y * BZ + threadIdx.y, y = blockIdx.z;
-    if (x >= P.nx || z >= P.nz) return;
+    __shared__ double s_phi[HN];
+    __shared__ uint8_t s_w[HN];
+    const int x0 = blockIdx.x * BX, z0 = blockIdx.y * BZ, y = blockIdx.z;
+    const int tid = threadIdx.y * BX + threadIdx.x;
+    for (int e = tid; e < HN; e += BX * BZ) {
+        const int dy = e / (HZ * HX), r = e - dy * (HZ * HX), ez = r / HX, ex = r - ez * HX;
+        const int xx = ((x0 - 1 + ex) % P.nx + P.nx) % P.nx, zz = ((z0 - 1 + ez) % P.nz + P.nz) % P.nz;
+        const int yy = y - 1 + dy;
+        const bool beyond = (yy < 0 || yy >= P.ny) && P.bc_open;
+        s_phi[e] = phi[nodek(P, xx, stencil_row(P, yy), zz)];
+        s_w[e] = beyond ? kBeyond : wall[nodek(P, xx, wrapi(yy, P.ny), zz)];
+    }
+    __syncthreads();
+    const int x = x0 + threadIdx.x, z = z0 + threadIdx.y;
+    const int lc = (HZ + threadIdx.y + 1) * HX + threadIdx.x + 1;   // LDS index of this node (middle slice)
+    if (x >= P.nx || z >= P.nz || s_w[lc]) return;
     const size_t k = nodek(P, x, y, z);
-    if (wall[k]) return;
     const size_t pl = P.plane;
     const float* Ag = A + (size_t)Q * pl;
     float* Bg = B + (size_t)Q * pl;
@@ -153,7 +171,26 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
 #pragma unroll
     for (int i = 0; i < QG; ++i) g[i] = Ag[i * pl + k];
 
-    const Phi3 ph = phi_fields(P, phi, x, y, z);
+    auto lds = [&](int i) { return lc + CY[i] * (HZ * HX) + CZ[i] * HX + CX[i]; };
+    Phi3 ph;
+    {
+        const double p0 = s_phi[lc];
+        double sx = 0.0, sy = 0.0, sz = 0.0, sl = 0.0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const double pn = s_phi[lds(i)];
+            const double wp = wtd(i) * pn;
+            if (CX[i]) sx += CX[i] * wp;
+            if (CY[i]) sy += CY[i] * wp;
+            if (CZ[i]) sz += CZ[i] * wp;
+            sl += wtd(i) * (pn - p0);
+        }
+        ph.phi = p0;
+        ph.gx = 3.0 * sx;
+        ph.gy = 3.0 * sy;
+        ph.gz = 3.0 * sz;
+        ph.mu = P.beta4 * p0 * ((p0 - P.phi_star) * (p0 + P.phi_star)) - P.kappa * (6.0 * sl);
+    }
     double Fx = ph.mu * ph.gx, Fy = ph.mu * ph.gy, Fz = ph.mu * ph.gz;
     if (y < P.force_rows) Fy += (double)fb;
     const float fx = (float)Fx, fy = (float)Fy, fz = (float)Fz;
@@ -195,15 +232,12 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
             B[k] = fs;
             continue;
         }
-        const int yd = y + CY[i];
-        if (yd < 0 || yd >= P.ny) {
-            if (P.bc_open) continue;
-        }
-        const size_t kd = nodek(P, wrapi(x + CX[i], P.nx), wrapi(yd, P.ny), wrapi(z + CZ[i], P.nz));
-        if (wall[kd])
+        const uint8_t wd = s_w[lds(i)];
+        if (wd == kBeyond) continue;
+        if (wd)
             B[OPP[i] * pl + k] = fs;
         else
-            B[i * pl + kd] = fs;
+            B[i * pl + nodek(P, wrapi(x + CX[i], P.nx), wrapi(y + CY[i], P.ny), wrapi(z + CZ[i], P.nz))] = fs;
     }
 
     // g: equilibrium of Eqs. 9-10 on D3Q7, h = g* - (1-q) g, and the
@@ -219,15 +253,14 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
             Bg[k] = h + P.omq * g[0];
             continue;
         }
-        const int yd = y + CY[i];
-        if (yd < 0 || yd >= P.ny) {
-            if (P.bc_open) continue;
-        }
-        const size_t kd = nodek(P, wrapi(x + CX[i], P.nx), wrapi(yd, P.ny), wrapi(z + CZ[i], P.nz));
-        if (wall[kd])
+        const uint8_t wd = s_w[lds(i)];
+        if (wd == kBeyond) continue;
+        if (wd) {
             Bg[OPP[i] * pl + k] = h + P.omq * g[OPP[i]];
-        else
+        } else {
+            const size_t kd = nodek(P, wrapi(x + CX[i], P.nx), wrapi(y + CY[i], P.ny), wrapi(z + CZ[i], P.nz));
             Bg[i * pl + kd] = h + P.omq * Ag[i * pl + kd];
+        }
     }
 }
 
