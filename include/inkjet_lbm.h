@@ -395,7 +395,8 @@ typedef struct ij3_params {
 typedef struct ij3_sim ij3_sim;
 
 /* Validate *p and allocate, on the current device, two distribution buffers
- * (19 + 7 float planes of ny*nz rows, row pitch nx rounded up to 64), the
+ * (26 floats per node: the 19 f and 7 g rows of each lattice row (y, z) are
+ * stored one after the other, row pitch nx rounded up to 64), the
  * phi field (double) and the wall mask from `wall` (host, [ny][nz][nx]
  * bytes, IJ_FLUID / IJ_WALL_INNER / IJ_WALL_OUTER; NULL: all fluid).  With
  * open rows, a fluid node of row 0 (ny-1) must have fluid directly above

@@ -6,8 +6,12 @@
 // Results, "Actuation modeling" (Fig. 1), and the wetting walls of
 // "Reproducing the experiment", written on three-dimensional lattices.
 //
-// Storage: two buffers of 26 float planes (f_0..f_18, then g_0..g_6), node
-// k = (y*nz + z)*pitch + x with the row pitch nx rounded up to 64.  f is
+// Storage: two buffers of 26 float populations per node (f_0..f_18, then
+// g_0..g_6).  The populations of one lattice row (fixed y, z) are 26
+// consecutive rows of pitch floats (nx rounded up to 64): population i of
+// node x of row r = y*nz + z sits at (r*26 + i)*pitch + x, so a workgroup's
+// 26 streams lie in one contiguous region of memory.  The wall mask and phi
+// are plain [y][z][pitch] arrays (node k = r*pitch + x).  f is
 // stored shifted by w_i n0 (the equilibrium of the mean density at rest), so
 // that float carries the deviations that the collision works on.  phi, its
 // wetting ghosts, the stencils and mu are double precision.
@@ -45,7 +49,7 @@ constexpr int BX = 64, BZ = 4;   // workgroup: 64 x-lanes (one wave) by 4 z-rows
 
 struct K3 {
     int nx, ny, nz, pitch;
-    size_t plane;     // floats per plane: ny * nz * pitch
+    size_t plane;     // nodes, row padding included: ny * nz * pitch
     int bc_open, force_rows;
     double phi_star, n0, beta4, kappa, q;
     double wet[3];    // ghost offsets 2 Omega phi* / W of wall classes 1, 2
@@ -53,6 +57,11 @@ struct K3 {
 };
 
 __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+// population i (0..18 f, 19..25 g) of node k (column x)
+__device__ __forceinline__ size_t pidx(const K3& P, size_t k, int x, int i)
+{
+    return (k - (size_t)x) * NPL + (size_t)i * P.pitch + (size_t)x;
+}
 __device__ __forceinline__ size_t nodek(const K3& P, int x, int y, int z)
 {
     return ((size_t)y * P.nz + z) * P.pitch + x;
@@ -74,10 +83,9 @@ __global__ __launch_bounds__(BX* BZ) void k3_phi(K3 P, const float* __restrict__
     if (x >= P.nx || z >= P.nz) return;
     const size_t k = nodek(P, x, y, z);
     if (wall[k]) return;
-    const float* g = A + (size_t)Q * P.plane;
     double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < QG; ++i) s += (double)g[i * P.plane + k];
+    for (int i = 0; i < QG; ++i) s += (double)A[pidx(P, k, x, Q + i)];
     phi[k] = s;
 }
 
@@ -161,15 +169,11 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
     const int lc = (HZ + threadIdx.y + 1) * HX + threadIdx.x + 1;   // LDS index of this node (middle slice)
     if (x >= P.nx || z >= P.nz || s_w[lc]) return;
     const size_t k = nodek(P, x, y, z);
-    const size_t pl = P.plane;
-    const float* Ag = A + (size_t)Q * pl;
-    float* Bg = B + (size_t)Q * pl;
-
     float f[Q], g[QG];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = A[i * pl + k];
+    for (int i = 0; i < Q; ++i) f[i] = A[pidx(P, k, x, i)];
 #pragma unroll
-    for (int i = 0; i < QG; ++i) g[i] = Ag[i * pl + k];
+    for (int i = 0; i < QG; ++i) g[i] = A[pidx(P, k, x, Q + i)];
 
     auto lds = [&](int i) { return lc + CY[i] * (HZ * HX) + CZ[i] * HX + CX[i]; };
     Phi3 ph;
@@ -229,15 +233,17 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
         const float S = pref * wt(i) * 3.f * ((cF - uF) + 3.f * cu * cF);
         const float fs = f[i] + (feq - f[i]) * inv_tau + S;
         if (i == 0) {
-            B[k] = fs;
+            B[pidx(P, k, x, 0)] = fs;
             continue;
         }
         const uint8_t wd = s_w[lds(i)];
         if (wd == kBeyond) continue;
-        if (wd)
-            B[OPP[i] * pl + k] = fs;
-        else
-            B[i * pl + nodek(P, wrapi(x + CX[i], P.nx), wrapi(y + CY[i], P.ny), wrapi(z + CZ[i], P.nz))] = fs;
+        if (wd) {
+            B[pidx(P, k, x, OPP[i])] = fs;
+        } else {
+            const int xd = wrapi(x + CX[i], P.nx);
+            B[pidx(P, nodek(P, xd, wrapi(y + CY[i], P.ny), wrapi(z + CZ[i], P.nz)), xd, i)] = fs;
+        }
     }
 
     // g: equilibrium of Eqs. 9-10 on D3Q7, h = g* - (1-q) g, and the
@@ -250,16 +256,17 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
         const float gs = g[i] + (geq - g[i]) * P.inv_tau_phi;
         const float h = gs - P.omq * g[i];
         if (i == 0) {
-            Bg[k] = h + P.omq * g[0];
+            B[pidx(P, k, x, Q)] = h + P.omq * g[0];
             continue;
         }
         const uint8_t wd = s_w[lds(i)];
         if (wd == kBeyond) continue;
         if (wd) {
-            Bg[OPP[i] * pl + k] = h + P.omq * g[OPP[i]];
+            B[pidx(P, k, x, Q + OPP[i])] = h + P.omq * g[OPP[i]];
         } else {
-            const size_t kd = nodek(P, wrapi(x + CX[i], P.nx), wrapi(y + CY[i], P.ny), wrapi(z + CZ[i], P.nz));
-            Bg[i * pl + kd] = h + P.omq * Ag[i * pl + kd];
+            const int xd = wrapi(x + CX[i], P.nx);
+            const size_t pd = pidx(P, nodek(P, xd, wrapi(y + CY[i], P.ny), wrapi(z + CZ[i], P.nz)), xd, Q + i);
+            B[pd] = h + P.omq * A[pd];
         }
     }
 }
@@ -274,12 +281,11 @@ __global__ void k3_open(K3 P, float* __restrict__ B, const uint8_t* __restrict__
     const size_t k = nodek(P, x, top ? P.ny - 1 : 0, z);
     const size_t kin = nodek(P, x, top ? P.ny - 2 : 1, z);
     if (wall[k]) return;
-    const size_t pl = P.plane;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         if (top ? CY[i] < 0 : CY[i] > 0) {
-            B[i * pl + k] = B[i * pl + kin];
-            if (i < QG) B[(Q + i) * pl + k] = B[(Q + i) * pl + kin];
+            B[pidx(P, k, x, i)] = B[pidx(P, kin, x, i)];
+            if (i < QG) B[pidx(P, k, x, Q + i)] = B[pidx(P, kin, x, Q + i)];
         }
 }
 
@@ -303,9 +309,8 @@ __global__ void k3_init_eq(K3 P, float* __restrict__ A, const uint8_t* __restric
     const int x = blockIdx.x * BX + threadIdx.x, z = blockIdx.y * BZ + threadIdx.y, y = blockIdx.z;
     if (x >= P.nx || z >= P.nz) return;
     const size_t k = nodek(P, x, y, z);
-    const size_t pl = P.plane;
     if (wall[k]) {
-        for (int i = 0; i < NPL; ++i) A[i * pl + k] = 0.f;
+        for (int i = 0; i < NPL; ++i) A[pidx(P, k, x, i)] = 0.f;
         return;
     }
     const size_t ke = ((size_t)y * P.nz + z) * P.nx + x;
@@ -316,13 +321,13 @@ __global__ void k3_init_eq(K3 P, float* __restrict__ A, const uint8_t* __restric
     for (int i = 0; i < Q; ++i) {
         const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
         const float a = i == 0 ? -6.f * pm : 3.f * pm;
-        A[i * pl + k] = wt(i) * (a + n * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
+        A[pidx(P, k, x, i)] = wt(i) * (a + n * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
     }
     const float gmu = P.gamma * (float)ph.mu, phif = (float)ph.phi;
 #pragma unroll
     for (int i = 0; i < QG; ++i) {
         const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-        A[(Q + i) * pl + k] = i == 0 ? phif - 3.f * gmu : 0.5f * gmu + phif * cu * P.inv_2q;
+        A[pidx(P, k, x, Q + i)] = i == 0 ? phif - 3.f * gmu : 0.5f * gmu + phif * cu * P.inv_2q;
     }
 }
 
@@ -340,7 +345,7 @@ __device__ __forceinline__ Mac3 node_macro(const K3& P, const float* __restrict_
     float dn = 0.f, jx = 0.f, jy = 0.f, jz = 0.f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const float f = A[i * P.plane + k];
+        const float f = A[pidx(P, k, x, i)];
         dn += f;
         if (CX[i]) jx += CX[i] * f;
         if (CY[i]) jy += CY[i] * f;
@@ -386,14 +391,14 @@ __global__ void k3_state_io(K3 P, float* __restrict__ A, const uint8_t* __restri
     const size_t ne = (size_t)P.ny * P.nz * P.nx;
     const size_t ke = ((size_t)y * P.nz + z) * P.nx + x;
     const bool solid = wall[k] != 0;
-    float* planes = is_f ? A : A + (size_t)Q * P.plane;
-    const int nq = is_f ? Q : QG;
+    const int nq = is_f ? Q : QG, i0 = is_f ? 0 : Q;
     for (int i = 0; i < nq; ++i) {
         const float shift = is_f ? wt(i) * P.n0f : 0.f;
+        const size_t pk = pidx(P, k, x, i0 + i);
         if (to_ext)
-            ext[i * ne + ke] = solid ? 0.f : planes[i * P.plane + k] + shift;
+            ext[i * ne + ke] = solid ? 0.f : A[pk] + shift;
         else if (!solid)
-            planes[i * P.plane + k] = ext[i * ne + ke] - shift;
+            A[pk] = ext[i * ne + ke] - shift;
     }
 }
 
