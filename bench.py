@@ -244,6 +244,58 @@ def surrogate_bench(queries: int = 100000, held: int = 256) -> dict:
             "gain": round(with_cph / solver_cph, 3)}
 
 
+BYTES_PER_NODE_3D = 208   # 19 + 7 float populations read and written per fluid node
+
+
+def round_nozzle_3d_bench(steps: int = 300, warmup: int = 20, oracle: bool = True) -> dict:
+    """The three-dimensional lattice (D3Q19 f, D3Q7 g): a 256 x 512 x 256
+    round nozzle, one step = phi, ghosts, the collide-and-push launch and the
+    open rows."""
+    import torch
+    import workloads as W
+    from paper_1702_04487_amd import lbm3d
+    c = W.config_round_nozzle()
+    p, wall = c["params"], c["wall"]
+    fluid = int((wall == 0).sum())
+    g = lbm3d.Sim3D(p, wall)
+    g.init_distance(c["distance"])
+    log(f"3-D round nozzle {p['nx']}x{p['ny']}x{p['nz']}: {warmup} warm-up steps, then {steps} timed")
+    g.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    s = g.sample(c["row0"])
+    g.close()
+    achieved = BYTES_PER_NODE_3D * fluid / (ms * 1e-3) / 1e9
+    out = {"workload": f"round nozzle {p['nx']}x{p['ny']}x{p['nz']} (bore radius {c['nozzle'][0]:g}, "
+                       f"length {c['nozzle'][1]}, contact angles 60/120, pulse)",
+           "fluid_nodes": fluid, "steps": steps, "ms_per_step": round(ms, 5),
+           "mlups": round(fluid / (ms * 1e-3) / 1e6, 1),
+           "algorithmic_gbs": round(achieved, 1), "frac_of_8tbs": round(achieved / HBM_PEAK_GBS, 4),
+           "bytes_per_node": BYTES_PER_NODE_3D, "nan_count": s["nan_count"], "max_u": s["max_u"]}
+    if oracle:
+        from oracle import oracle3d as O3
+        n3 = 64
+        band = dict(p, nx=n3, nz=n3, ny=64)
+        wb = W.round_nozzle_wall3d(n3, 64, n3, 16.0, 32)
+        o = O3.Oracle3D(band, wb)
+        o.init_distance(W.meniscus_distance3d(n3, 64, n3, 32))
+        o.step(1)
+        t0 = time.perf_counter()
+        o.step(5)
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"mlups": round(int((wb == 0).sum()) * 5 / dt / 1e6, 3),
+                             "sample": "64x64x64 round nozzle (bore radius 16), 5 FP64 steps after 1 warm-up",
+                             "threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -251,6 +303,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep cases/hour measurement")
+    ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional round-nozzle leg")
     ap.add_argument("--kernel-steps", type=int, default=500,
                     help="launches timed back-to-back for the fused kernel's mean duration")
     ap.add_argument("--tiling", default="",
@@ -346,6 +399,8 @@ def main() -> int:
     }
     sim.close()
     del sim
+    if not args.no_3d:
+        out["round_nozzle_3d"] = round_nozzle_3d_bench(oracle=not args.no_cpu_baseline)
     if not args.no_sweep:
         out["sweep"] = sweep_bench()
         out["sweep"]["surrogate"] = surrogate_bench()
