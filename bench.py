@@ -42,8 +42,8 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1702_04487_amd", "csrc", "lbm_core.hip
 # kernel source with this SHA-256 only; for any other it is reported as null.
 MEASURED_TRAFFIC = {
     "kernel_source_sha256": "2e87311cac29df032befe608ce6e7e9b880a30ef9ebcc71ffc450300cecc56b5",
-    "read_bytes": 2068843049,
-    "write_bytes": 1978647902,
+    "read_bytes": 2069104610,
+    "write_bytes": 1978847421,
 }
 
 
