@@ -96,3 +96,33 @@ def test_largest_lattice_is_accepted():
     n = ctypes.c_size_t(0)
     assert L.ij_required_bytes(ctypes.byref(p), ctypes.byref(n)) == lbm.IJ_OK
     assert n.value == 65535 * 2048 * (14 * 4 + 2)
+
+
+def test_3d_invalid_parameters_are_rejected_without_a_device():
+    """ij3_create validates parameters and the open-row geometry on the host
+    before any device call."""
+    import numpy as np
+    from paper_1702_04487_amd import lbm, lbm3d
+    L = lbm.load()
+    c = W.config_round_nozzle_small()
+    good = c["params"]
+    bad_cases = [dict(good, nz=2), dict(good, nx=2), dict(good, tau_phi=0.5), dict(good, rho_amb=1.5),
+                 dict(good, width=-1.0), dict(good, theta_outer=-3.0), dict(good, bc_y=5),
+                 dict(good, t_idle=-1), dict(good, nx=70000)]
+    for bad in bad_cases:
+        p = lbm3d.to_params3(bad)
+        h = ctypes.c_void_p()
+        assert L.ij3_create(ctypes.byref(p), None, ctypes.byref(h)) == lbm.IJ_ERR_INVALID_ARG, bad
+        assert not h.value
+        assert L.ij3_last_error(None)
+    wall = c["wall"].copy()
+    wall[1, 10, 16] = W.WALL_OUTER          # open bottom row: fluid with a wall directly above
+    wall[0, 10, 16] = W.FLUID
+    h = ctypes.c_void_p()
+    p = lbm3d.to_params3(good)
+    r = L.ij3_create(ctypes.byref(p), np.ascontiguousarray(wall).ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
+    assert r == lbm.IJ_ERR_INVALID_ARG and b"open row" in L.ij3_last_error(None)
+    wall = c["wall"].copy()
+    wall[5, 5, 5] = 7
+    r = L.ij3_create(ctypes.byref(p), np.ascontiguousarray(wall).ctypes.data_as(ctypes.c_void_p), ctypes.byref(h))
+    assert r == lbm.IJ_ERR_INVALID_ARG
