@@ -435,9 +435,10 @@ def meniscus_distance3d(nx: int, ny: int, nz: int, length: int) -> np.ndarray:
 
 
 def spheres_distance3d(nx: int, ny: int, nz: int, spheres: Sequence[Tuple[float, float, float, float]],
-                       far: float = -1.0e3) -> np.ndarray:
+                       far: float = -1.0e3, periodic_y: bool = True) -> np.ndarray:
     """Signed distance to a union of spheres (cx, cy, cz, r) in a box periodic
-    in all three directions (max over spheres of r - |x - c|, nearest image)."""
+    in x and z, and in y unless periodic_y is False (max over spheres of
+    r - |x - c|, nearest image)."""
     y, z, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nz, dtype=np.float64),
                           np.arange(nx, dtype=np.float64), indexing="ij")
     d = np.full((ny, nz, nx), far, dtype=np.float64)
@@ -445,7 +446,8 @@ def spheres_distance3d(nx: int, ny: int, nz: int, spheres: Sequence[Tuple[float,
         dx = np.abs(x - cx)
         dx = np.minimum(dx, nx - dx)
         dy = np.abs(y - cy)
-        dy = np.minimum(dy, ny - dy)
+        if periodic_y:
+            dy = np.minimum(dy, ny - dy)
         dz = np.abs(z - cz)
         dz = np.minimum(dz, nz - dz)
         d = np.maximum(d, r - np.sqrt(dx * dx + dy * dy + dz * dz))
