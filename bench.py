@@ -245,6 +245,25 @@ def surrogate_bench(queries: int = 100000, held: int = 256) -> dict:
 
 
 BYTES_PER_NODE_3D = 208   # 19 + 7 float populations read and written per fluid node
+KERNEL_SOURCE_3D = os.path.join(ROOT, "paper_1702_04487_amd", "csrc", "lbm3d.hip")
+# HBM bytes of one step of the 256 x 512 x 256 round nozzle (k3_phi, k3_ghost,
+# k3_collide, k3_open), from rocprofv3 FETCH_SIZE (x 2.000) and WRITE_SIZE
+# (x 1.000) runs of this script, scaled as for the two-dimensional kernel;
+# valid for the kernel source with this SHA-256 only.
+MEASURED_TRAFFIC_3D = {
+    "kernel_source_sha256": "babd135816f4ea0d57860531986196e1557a1795b1b04e9924bcb9196e3aba61",
+    "read_bytes": 4723075126,
+    "write_bytes": 3024961472,
+}
+
+
+def measured_traffic_3d():
+    import hashlib
+    with open(KERNEL_SOURCE_3D, "rb") as fh:
+        digest = hashlib.sha256(fh.read()).hexdigest()
+    if digest != MEASURED_TRAFFIC_3D["kernel_source_sha256"]:
+        return None
+    return MEASURED_TRAFFIC_3D["read_bytes"] + MEASURED_TRAFFIC_3D["write_bytes"]
 
 
 def round_nozzle_3d_bench(steps: int = 300, warmup: int = 20, oracle: bool = True) -> dict:
@@ -273,12 +292,17 @@ def round_nozzle_3d_bench(steps: int = 300, warmup: int = 20, oracle: bool = Tru
     s = g.sample(c["row0"])
     g.close()
     achieved = BYTES_PER_NODE_3D * fluid / (ms * 1e-3) / 1e9
+    traffic = measured_traffic_3d()
     out = {"workload": f"round nozzle {p['nx']}x{p['ny']}x{p['nz']} (bore radius {c['nozzle'][0]:g}, "
                        f"length {c['nozzle'][1]}, contact angles 60/120, pulse)",
            "fluid_nodes": fluid, "steps": steps, "ms_per_step": round(ms, 5),
            "mlups": round(fluid / (ms * 1e-3) / 1e6, 1),
            "algorithmic_gbs": round(achieved, 1), "frac_of_8tbs": round(achieved / HBM_PEAK_GBS, 4),
-           "bytes_per_node": BYTES_PER_NODE_3D, "nan_count": s["nan_count"], "max_u": s["max_u"]}
+           "bytes_per_node": BYTES_PER_NODE_3D, "nan_count": s["nan_count"], "max_u": s["max_u"],
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                        "traffic_gbs": None if traffic is None else round(traffic / (ms * 1e-3) / 1e9, 1),
+                        "scope": "one whole step (k3_phi, k3_ghost, k3_collide, k3_open)"}}
     if oracle:
         from oracle import oracle3d as O3
         n3 = 64
