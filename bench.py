@@ -42,8 +42,8 @@ KERNEL_SOURCE = os.path.join(ROOT, "paper_1702_04487_amd", "csrc", "lbm_core.hip
 # kernel source with this SHA-256 only; for any other it is reported as null.
 MEASURED_TRAFFIC = {
     "kernel_source_sha256": "2e87311cac29df032befe608ce6e7e9b880a30ef9ebcc71ffc450300cecc56b5",
-    "read_bytes": 2069104610,
-    "write_bytes": 1978847421,
+    "read_bytes": 2073227987,
+    "write_bytes": 1978851363,
 }
 
 
@@ -246,14 +246,14 @@ def surrogate_bench(queries: int = 100000, held: int = 256) -> dict:
 
 BYTES_PER_NODE_3D = 208   # 19 + 7 float populations read and written per fluid node
 KERNEL_SOURCE_3D = os.path.join(ROOT, "paper_1702_04487_amd", "csrc", "lbm3d.hip")
-# HBM bytes of one step of the 256 x 512 x 256 round nozzle (k3_phi, k3_ghost,
+# HBM bytes of one step of the 256 x 512 x 256 round nozzle (k3_ghost_g,
 # k3_collide, k3_open), from rocprofv3 FETCH_SIZE (x 2.000) and WRITE_SIZE
 # (x 1.000) runs of this script, scaled as for the two-dimensional kernel;
 # valid for the kernel source with this SHA-256 only.
 MEASURED_TRAFFIC_3D = {
-    "kernel_source_sha256": "babd135816f4ea0d57860531986196e1557a1795b1b04e9924bcb9196e3aba61",
-    "read_bytes": 4723075126,
-    "write_bytes": 3024961472,
+    "kernel_source_sha256": "2e87311cac29df032befe608ce6e7e9b880a30ef9ebcc71ffc450300cecc56b5",
+    "read_bytes": 2073227987,
+    "write_bytes": 1978851363,
 }
 
 
@@ -302,7 +302,7 @@ def round_nozzle_3d_bench(steps: int = 300, warmup: int = 20, oracle: bool = Tru
            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                         "traffic_gbs": None if traffic is None else round(traffic / (ms * 1e-3) / 1e9, 1),
-                        "scope": "one whole step (k3_phi, k3_ghost, k3_collide, k3_open)"}}
+                        "scope": "one whole step (k3_ghost_g, k3_collide, k3_open)"}}
     if oracle:
         from oracle import oracle3d as O3
         n3 = 64

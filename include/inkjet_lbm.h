@@ -413,8 +413,9 @@ const char *ij3_last_error(const ij3_sim *s);
 ij_status ij3_init(ij3_sim *s, const float *src_dev, int32_t from_distance, const float *ux_dev,
                    const float *uy_dev, const float *uz_dev, void *stream);
 
-/* nsteps time steps (Eqs. 3, 4, 8): phi and its ghosts, then one fused
- * collide-and-push launch, then the open rows.  Asynchronous. */
+/* nsteps time steps (Eqs. 3, 4, 8): the wetting ghosts, then one fused
+ * launch that forms phi from g, collides and pushes, then the open rows.
+ * Asynchronous. */
 ij_status ij3_step(ij3_sim *s, int64_t nsteps, void *stream);
 int64_t ij3_time(const ij3_sim *s);
 

@@ -16,13 +16,16 @@
 // that float carries the deviations that the collision works on.  phi, its
 // wetting ghosts, the stencils and mu are double precision.
 //
-// One step is three launches: phi = sum g at fluid nodes, the ghost phi of
-// the solid nodes within reach of fluid, and one collide-and-push launch (a
+// One step is two launches: the ghost phi of the solid nodes within reach of
+// fluid (from their fluid neighbours' g), and one collide-and-push launch
+// whose workgroups build the phi of their tile and its halo from g in LDS (a
 // node collides f and g and pushes each post-collision population to its
 // destination, or back into its own opposite slot at a solid).  With open
-// rows a fourth launch copies the incoming populations of rows 0 and ny-1.
-// HBM-bound: 26 floats read and written per fluid node (208 B), plus the phi
-// field (8 B written, 8 B read) and the destinations' old g (cache hits).
+// rows a third launch copies the incoming populations of rows 0 and ny-1.
+// phi is written to memory only at ghost nodes, and as a whole field only
+// for readback (moments, diagnostics, the initial state).  HBM-bound: 26
+// floats read and written per fluid node (208 B), plus the halo's g and the
+// destinations' old g (mostly cache hits).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -116,6 +119,42 @@ __global__ void k3_ghost(K3 P, const int4* __restrict__ list, int n, const uint8
     phi[nodek(P, L.x, L.y, L.z)] = cnt ? sum / cnt + P.wet[L.w] : 0.0;
 }
 
+// phi = sum g of a fluid node, summed in the order of k3_phi
+__device__ __forceinline__ double phi_of_g(const K3& P, const float* __restrict__ A, size_t k, int x)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < QG; ++i) s += (double)A[pidx(P, k, x, Q + i)];
+    return s;
+}
+
+// the ghost of each listed solid node as k3_ghost computes it, with the
+// fluid neighbours' phi summed from their g
+__global__ void k3_ghost_g(K3 P, const int4* __restrict__ list, int n, const uint8_t* __restrict__ wall,
+                           const float* __restrict__ A, double* __restrict__ phi)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int4 L = list[e];
+    double sum = 0.0;
+    int cnt = 0;
+    for (int pass = 0; pass < 2 && cnt == 0; ++pass) {
+        const int i0 = pass == 0 ? 1 : 7, i1 = pass == 0 ? 7 : Q;
+        for (int i = i0; i < i1; ++i) {
+            const int yn = L.y + CY[i];
+            if (yn < 0 || yn >= P.ny) {
+                if (P.bc_open) continue;
+            }
+            const int xn = wrapi(L.x + CX[i], P.nx);
+            const size_t kn = nodek(P, xn, wrapi(yn, P.ny), wrapi(L.z + CZ[i], P.nz));
+            if (wall[kn]) continue;
+            sum += phi_of_g(P, A, kn, xn);
+            ++cnt;
+        }
+    }
+    phi[nodek(P, L.x, L.y, L.z)] = cnt ? sum / cnt + P.wet[L.w] : 0.0;
+}
+
 // phi, its gradient and Laplacian (isotropic D3Q19 sums) and mu at a fluid node
 struct Phi3 {
     double phi, mu, gx, gy, gz;
@@ -143,9 +182,10 @@ __device__ __forceinline__ Phi3 phi_fields(const K3& P, const double* __restrict
 }
 
 // collide every fluid node and push its populations (Eqs. 3, 4, 8).
-// The workgroup first stages phi and the wall bytes of its tile and a
-// one-node halo (three y-slices) in LDS: the stencil and the destination
-// checks then read LDS instead of issuing 36 scattered loads per node.
+// The workgroup first stages phi (sum g at fluid nodes, the ghost at solid
+// ones) and the wall bytes of its tile and a one-node halo (three y-slices)
+// in LDS: the stencil and the destination checks then read LDS instead of
+// issuing 36 scattered loads per node.
 constexpr int HX = BX + 2, HZ = BZ + 2, HN = 3 * HZ * HX;
 constexpr uint8_t kBeyond = 255;   // LDS wall byte of a node beyond an open row
 __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restrict__ A, float* __restrict__ B,
@@ -161,7 +201,8 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
         const int xx = ((x0 - 1 + ex) % P.nx + P.nx) % P.nx, zz = ((z0 - 1 + ez) % P.nz + P.nz) % P.nz;
         const int yy = y - 1 + dy;
         const bool beyond = (yy < 0 || yy >= P.ny) && P.bc_open;
-        s_phi[e] = phi[nodek(P, xx, stencil_row(P, yy), zz)];
+        const size_t ks = nodek(P, xx, stencil_row(P, yy), zz);
+        s_phi[e] = wall[ks] ? phi[ks] : phi_of_g(P, A, ks, xx);
         s_w[e] = beyond ? kBeyond : wall[nodek(P, xx, wrapi(yy, P.ny), zz)];
     }
     __syncthreads();
@@ -716,7 +757,9 @@ ij_status ij3_step(ij3_sim* s, int64_t nsteps, void* stream)
     hipStream_t st = (hipStream_t)stream;
     const K3& K = s->K;
     for (int64_t n = 0; n < nsteps; ++n) {
-        if (ij_status e = refresh_phi(s, st)) return e;
+        if (s->n_ghost)
+            hipLaunchKernelGGL(k3_ghost_g, dim3((s->n_ghost + 255) / 256), dim3(256), 0, st, K, s->ghost,
+                               s->n_ghost, s->wall, s->buf[s->cur], s->phi);
         const float fb = (float)pulse(s->p, s->t);
         hipLaunchKernelGGL(k3_collide, grid_of(K, K.ny), dim3(BX, BZ), 0, st, K, s->buf[s->cur],
                            s->buf[1 - s->cur], s->wall, s->phi, fb);
