@@ -48,7 +48,7 @@ constexpr int OPP[Q] = {0, 3, 4, 1, 2, 6, 5, 9, 10, 7, 8, 13, 14, 11, 12, 17, 18
 __host__ __device__ constexpr float wt(int i) { return i == 0 ? 1.f / 3.f : (i < 7 ? 1.f / 18.f : 1.f / 36.f); }
 __host__ __device__ constexpr double wtd(int i) { return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0); }
 
-constexpr int BX = 64, BZ = 4;   // workgroup: 64 x-lanes (one wave) by 4 z-rows
+constexpr int BX = 128, BZ = 4;   // workgroup: 128 x-lanes (two waves) by 4 z-rows
 
 struct K3 {
     int nx, ny, nz, pitch;
