@@ -478,7 +478,7 @@ __global__ __launch_bounds__(DT) void k3_rows(K3 P, const float* __restrict__ A,
     __shared__ Row3 s[DT];
     s[threadIdx.x] = a;
     __syncthreads();
-    for (int h = DT / 2; h > 0; h >>= 1) {
+    for (unsigned h = DT / 2; h > 0; h >>= 1) {
         if (threadIdx.x < h) {
             Row3& l = s[threadIdx.x];
             const Row3& r = s[threadIdx.x + h];

@@ -289,3 +289,26 @@ def test_sessile_drop_contact_angle_3d(gpu_lib, theta):
     ang_z = _cap_angle(phi[:, :, nx // 2], nz // 2)
     print("angles", ang_x, ang_z)
     assert ang_x == pytest.approx(theta, abs=3.0) and ang_z == pytest.approx(theta, abs=3.0)
+
+
+def test_round_nozzle_ejects_ink(gpu_lib):
+    """A push and a pull through the 16-radius round bore: the column of ink
+    above the exit pinches off from the bore (a detached run of ink rows
+    above the exit, from the per-slice ink counts of ij3_sample) between
+    steps 12 000 and 18 000, with no non-finite node and speeds below 0.2."""
+    print("3-D ejection 128x512x128", flush=True)
+    from oracle.oracle import segments
+    from paper_1702_04487_amd import lbm3d
+    c = W.config_round_nozzle_eject()
+    g = lbm3d.Sim3D(c["params"], c["wall"])
+    g.init_distance(c["distance"])
+    first = None
+    while g.t < c["steps"]:
+        g.step(500)
+        s = g.sample(c["row0"])
+        assert s["nan_count"] == 0 and s["max_u"] < 0.2, (g.t, s["max_u"])
+        seg = segments(s["row_count"], s["row_uy"], c["row0"], 4 * c["params"]["width"] ** 3)
+        if seg["n_detached"] and first is None:
+            first = g.t
+            print("detached at", first, "ink nodes", seg["largest_count"], flush=True)
+    assert first is not None and 12000 <= first <= 18000, first

@@ -473,10 +473,26 @@ def config_round_nozzle_small() -> dict:
 
 def config_round_nozzle(nx: int = 256, ny: int = 512, nz: int = 256) -> dict:
     """256 x 512 x 256 round nozzle (33.6 M nodes, the node count of the
-    2048 x 16384 droplet field): bore radius 32 and length 128, the small
-    case's fluid and pulse with durations scaled to the larger bore."""
+    2048 x 16384 droplet field): bore radius 32 and length 128, the ejecting
+    case's fluid (Gamma 0.5), its pulse scaled by (16/32)^2 to the same
+    viscous speed bound in the wider bore, durations by 2^2."""
     r, L = 32.0, 128
-    p = base_params3d(nx, ny, nz, force_rows=L, t_pos=2000, t_neg=1000, t_idle=57000, f_pos=2e-4,
-                      f_neg=1e-4, tau_ink=0.8, theta_inner=60.0, theta_outer=120.0)
+    p = base_params3d(nx, ny, nz, force_rows=L, t_pos=32000, t_neg=12000, t_idle=10 ** 6, f_pos=3e-5,
+                      f_neg=3e-5, tau_ink=0.8, theta_inner=60.0, theta_outer=120.0, gamma=0.5)
     return dict(name=f"round_nozzle_{nx}x{ny}x{nz}", params=p, wall=round_nozzle_wall3d(nx, ny, nz, r, L),
                 distance=meniscus_distance3d(nx, ny, nz, L), row0=L, steps=60000, nozzle=(r, L))
+
+
+def config_round_nozzle_eject() -> dict:
+    """128 x 512 x 128 round nozzle that ejects ink: bore radius 16 and
+    length 96, density 1.0/0.1, tau 0.8 ink / 1.0 ambient, sigma 0.01,
+    Gamma 0.5 (at Gamma 1 the three-dimensional update blows up at the
+    interface), contact angles 60 (bore) and 120 (plate); push +1.2e-4 for
+    8000 steps (speed about 0.14, near the viscous bound of the bore), pull
+    -1.2e-4 for 3000, idle; the neck pinches off near step 15 500."""
+    nx = nz = 128
+    ny, r, L = 512, 16.0, 96
+    p = base_params3d(nx, ny, nz, force_rows=L, t_pos=8000, t_neg=3000, t_idle=10 ** 6, f_pos=1.2e-4,
+                      f_neg=1.2e-4, tau_ink=0.8, theta_inner=60.0, theta_outer=120.0, gamma=0.5)
+    return dict(name="round_nozzle_eject_128x512x128", params=p, wall=round_nozzle_wall3d(nx, ny, nz, r, L),
+                distance=meniscus_distance3d(nx, ny, nz, L), row0=L, steps=18000, nozzle=(r, L))
