@@ -312,3 +312,29 @@ def test_round_nozzle_ejects_ink(gpu_lib):
             first = g.t
             print("detached at", first, "ink nodes", seg["largest_count"], flush=True)
     assert first is not None and 12000 <= first <= 18000, first
+
+
+def test_degenerate_lattices(oracle3d_mod, gpu_lib):
+    """Edge cases: a lattice with no fluid node steps and samples to zeros;
+    the smallest open lattice (3 x 3 x 3, one interior row) and a lattice
+    with no solid node (an empty ghost list) match the oracle."""
+    print("3-D degenerate lattices", flush=True)
+    from paper_1702_04487_amd import lbm3d
+    p = W.base_params3d(5, 4, 3, bc_y=W.BC_PERIODIC)
+    solid = np.full((4, 3, 5), W.WALL_OUTER, np.uint8)
+    g = lbm3d.Sim3D(p, solid)
+    g.init_distance(np.zeros((4, 3, 5)))
+    g.step(3)
+    s = g.sample()
+    assert s["mass_n"] == 0.0 and s["mass_phi"] == 0.0 and s["nan_count"] == 0 and g.t == 3
+    f, gg = g.state()
+    assert float(f.abs().max()) == 0.0 and float(gg.abs().max()) == 0.0
+    for p, d in [(W.base_params3d(3, 3, 3, bc_y=W.BC_OPEN, force_rows=3, f_pos=1e-4, t_pos=10 ** 6),
+                  np.broadcast_to(1.2 - np.arange(3.0)[:, None, None], (3, 3, 3)).copy()),
+                 (W.base_params3d(9, 7, 5, bc_y=W.BC_PERIODIC, gamma=0.5),
+                  W.spheres_distance3d(9, 7, 5, [(4.0, 3.0, 2.0, 2.5)]))]:
+        wall = np.zeros((p["ny"], p["nz"], p["nx"]), np.uint8)
+        o, g = _pair(oracle3d_mod, p, wall, d)
+        o.step(10)
+        g.step(10)
+        _compare_state(o, g, 2e-6)
