@@ -147,8 +147,9 @@ ij_status build_tiles(ij_batch* b)
             for (int k = 0; k < s->n_strips; ++k)
                 if (s->tile_plain[(size_t)rb * s->n_strips + k]) {
                     const int y0 = rb * s->rows_per_block, h = std::min(s->ny - y0, s->rows_per_block);
+                    // bit 30: an odd row block (it may walk its rows downwards)
                     lists[k < s->n_wide ? 0 : 1].push_back(
-                        make_int4((int)c, k, y0 | (h << 16), s->strip_x0[(size_t)k]));
+                        make_int4((int)c, k, y0 | (h << 16) | ((rb & 1) << 30), s->strip_x0[(size_t)k]));
                 }
         for (const int4& g : s->gtiles_host) lists[2].push_back(make_int4((int)c, g.x, g.y | (g.w << 16), g.z));
     }

@@ -1305,9 +1305,11 @@ __device__ __forceinline__ double case_pulse(const CaseRec& c, int64_t t)
 }
 
 // Workgroup b runs tiles [b * per_wg, (b + 1) * per_wg) of the (case,
-// strip, first row | rows << 16, first column) list, in order (neighbouring
-// tiles of a case share their halo rows through the cache); a launch takes
-// the tiles of its own width (64 * NW columns).
+// strip, first row | rows << 16 | odd block << 30, first column) list, in
+// order (neighbouring tiles of a case share their halo rows through the
+// cache); a launch takes the tiles of its own width (64 * NW columns).  With
+// one tile per workgroup, odd row blocks walk down, as in the single-lattice
+// launch (consecutive workgroups then meet in their shared halo rows).
 template <int NW, bool PLAIN>
 __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __restrict__ cases,
                                                            const int4* __restrict__ tiles, int n_tiles,
@@ -1315,16 +1317,18 @@ __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __rest
                                                            const int* __restrict__ active)
 {
     const int64_t t = *t_dev;
+    const bool single = per_wg == 1;
     const int i0 = blockIdx.x * per_wg, i1 = min(n_tiles, i0 + per_wg);
     for (int i = i0; i < i1; ++i) {
-        const int4 tl = tiles[i];   // (case, strip, first row | rows << 16, first column)
+        const int4 tl = tiles[i];
         if (!active[tl.x]) continue;
         const CaseRec& R = cases[tl.x];
         const KParams P = R.P;
         const float fb = (float)case_pulse(R, t);
         const int y0 = tl.z & 0xffff;
+        const bool down = single && ((tl.z >> 30) & 1);
         collide_tile<NW, PLAIN>(P, fb, R.buf[parity], R.buf[1 - parity], R.wall, R.plain, tl.y, tl.w, y0,
-                                y0 + (tl.z >> 16));
+                                y0 + ((tl.z >> 16) & 0x3fff), nullptr, down);
     }
 }
 
