@@ -338,3 +338,29 @@ def test_degenerate_lattices(oracle3d_mod, gpu_lib):
         o.step(10)
         g.step(10)
         _compare_state(o, g, 2e-6)
+
+
+def test_checkpoint_resume(gpu_lib):
+    """A run stopped at step 40, read out through ij3_get_state and resumed in
+    a new handle through ij3_set_state, ends where the uninterrupted run
+    ends (to the float rounding of removing and restoring the stored shift
+    of f)."""
+    print("3-D checkpoint / resume", flush=True)
+    from paper_1702_04487_amd import lbm3d
+    c = W.config_round_nozzle_small()
+    a = lbm3d.Sim3D(c["params"], c["wall"])
+    a.init_distance(c["distance"])
+    a.step(80)
+    fa, ga = a.state()
+    b = lbm3d.Sim3D(c["params"], c["wall"])
+    b.init_distance(c["distance"])
+    b.step(40)
+    f40, g40 = b.state()
+    r = lbm3d.Sim3D(c["params"], c["wall"])
+    r.set_state(f40, g40, t=40)
+    r.step(40)
+    assert r.t == 80
+    fr, gr = r.state()
+    fl = (c["wall"] == 0)[None]
+    assert np.abs(np.where(fl, _np(fr) - _np(fa), 0)).max() < 1e-6
+    assert np.abs(np.where(fl, _np(gr) - _np(ga), 0)).max() < 1e-6
