@@ -111,8 +111,8 @@ class Oracle3D:
             raise ValueError(f"o3_create failed (code {err.value})")
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().o3_destroy(self.h)
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.o3_destroy(self.h)
             self.h = None
 
     def __del__(self):

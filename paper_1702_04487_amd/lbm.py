@@ -83,6 +83,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise FileNotFoundError(f"{path} is missing: build it with `python -m paper_1702_04487_amd.build`")
+    # torch first: its HIP runtime must be the one the library binds to (a
+    # library loaded before torch pulls in the system runtime, and torch's
+    # own then finds no GPU)
+    import torch  # noqa: F401
     L = ctypes.CDLL(path)
     vp, i64, i32, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
     sig = {

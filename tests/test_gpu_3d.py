@@ -364,3 +364,31 @@ def test_checkpoint_resume(gpu_lib):
     fl = (c["wall"] == 0)[None]
     assert np.abs(np.where(fl, _np(fr) - _np(fa), 0)).max() < 1e-6
     assert np.abs(np.where(fl, _np(gr) - _np(ga), 0)).max() < 1e-6
+
+
+def paper_fluid_nozzle3d():
+    """A 40 x 72 x 40 round nozzle (bore radius 10, plate y < 24) with the
+    paper preset's fluid: densities 1000 / 1 (phi* = 499.5), W 3, sigma 1.08,
+    tau 0.85 / 0.8 and its mobility and pulse amplitudes (in steps)."""
+    pp = W.config_paper()["params"]
+    nx = nz = 40
+    ny, r, L = 72, 10.0, 24
+    p = W.base_params3d(nx, ny, nz, **{k: pp[k] for k in ("rho_ink", "rho_amb", "sigma", "width", "gamma",
+                                                          "tau_ink", "tau_amb", "tau_phi", "f_pos", "f_neg")})
+    p.update(force_rows=L, t_pos=200, t_neg=100, t_idle=10 ** 6, theta_inner=60.0, theta_outer=120.0)
+    return p, W.round_nozzle_wall3d(nx, ny, nz, r, L), W.meniscus_distance3d(nx, ny, nz, L)
+
+
+def test_paper_fluid_matches_oracle(oracle3d_mod, gpu_lib):
+    """At the paper's density ratio (phi* = 499.5) the rest population g_0 is
+    about phi; its float remainder keeps the 3-D path within 1e-5 relative L2
+    of the oracle through the pulse."""
+    print("3-D paper fluid", flush=True)
+    o, g = _pair(oracle3d_mod, *paper_fluid_nozzle3d())
+    worst = {}
+    for t in (100, 300):
+        o.step(t - o.t)
+        g.step(t - g.t)
+        for k, v in _compare_fields(o, g, 1e-5).items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    print("worst relative L2:", worst)
