@@ -102,18 +102,33 @@ def test_one_step_and_twenty_steps(oracle3d_mod, gpu_lib, name):
 
 def test_round_nozzle_pulse(oracle3d_mod, gpu_lib):
     """The 32 x 96 x 32 round nozzle through its +/- pulse (60 + 30 steps)
-    and after: fields within 1e-5 relative L2 at every checkpoint."""
-    print("3-D round nozzle 200 steps", flush=True)
+    and after: fields within 1e-5 relative L2 at every checkpoint to step
+    300.  At step 1000 n and phi still hold 1e-5; the velocity, which has
+    decayed tenfold to the spurious currents at the rim (max |u| ~ 1e-3), is
+    held to 1e-4: its error is the FP32 rounding of the populations
+    accumulated over 1000 steps (about 7e-8 absolute, sqrt(1000) times a
+    step's rounding), which a float remainder of g_0 does not change."""
+    print("3-D round nozzle 1000 steps", flush=True)
     c = W.config_round_nozzle_small()
     o, g = _pair(oracle3d_mod, c["params"], c["wall"], c["distance"])
     worst = {}
-    for t in (60, 90, 200):
+    for t in (60, 90, 200, 300):
         o.step(t - o.t)
         g.step(t - g.t)
         for k, v in _compare_fields(o, g, 1e-5).items():
             worst[k] = max(worst.get(k, 0.0), v)
-    print("worst relative L2:", worst)
-    assert np.max(np.abs(o.fields()["uy"])) > 1e-3   # the pulse moved the ink
+        if t == 90:
+            assert np.max(np.abs(o.fields()["uy"])) > 1e-3   # the pulse moved the ink
+    print("worst relative L2 to step 300:", worst)
+    o.step(1000 - o.t)
+    g.step(1000 - g.t)
+    mo = o.fields()
+    mg = {k: _np(v) for k, v in g.moments().items()}
+    fl = o.wall == 0
+    e = {k: rel_l2(mg[k][fl], mo[k][fl]) for k in ("n", "phi")}
+    e["u"] = rel_l2(np.stack([mg[k][fl] for k in ("ux", "uy", "uz")]), np.stack([mo[k][fl] for k in ("ux", "uy", "uz")]))
+    print("relative L2 at step 1000:", e)
+    assert e["n"] <= 1e-5 and e["phi"] <= 1e-5 and e["u"] <= 1e-4, e
 
 
 def test_diagnostics_match_oracle(oracle3d_mod, gpu_lib):

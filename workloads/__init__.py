@@ -462,11 +462,12 @@ def base_params3d(nx: int, ny: int, nz: int, **kw) -> dict:
 
 def config_round_nozzle_small() -> dict:
     """32 x 96 x 32 round nozzle (FP64 parity workload): bore radius 8 and
-    length 32, density 1.0/0.1, tau 0.8 ink / 1.0 ambient, contact angles 60
-    (bore) and 120 (plate), pulse +1e-3 for 60 steps, -5e-4 for 30, idle."""
+    length 32, density 1.0/0.1, tau 0.8 ink / 1.0 ambient, Gamma 0.5, contact
+    angles 60 (bore) and 120 (plate), pulse +1e-3 for 60 steps, -5e-4 for 30,
+    idle."""
     nx, ny, nz, r, L = 32, 96, 32, 8.0, 32
     p = base_params3d(nx, ny, nz, force_rows=L, t_pos=60, t_neg=30, t_idle=1000, f_pos=1e-3, f_neg=5e-4,
-                      tau_ink=0.8, theta_inner=60.0, theta_outer=120.0)
+                      tau_ink=0.8, theta_inner=60.0, theta_outer=120.0, gamma=0.5)
     return dict(name="round_nozzle_32x96x32", params=p, wall=round_nozzle_wall3d(nx, ny, nz, r, L),
                 distance=meniscus_distance3d(nx, ny, nz, L), row0=L, steps=200, nozzle=(r, L))
 
