@@ -334,8 +334,8 @@ def main() -> int:
                     help="waves_x,rows_per_block of the fused kernel (default: the library's choice)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the lattice update is measured on a single MI355X)", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus} is not supported: the lattice update is measured on a "
+              "single MI355X", file=sys.stderr)
         return 2
 
     import torch
