@@ -430,14 +430,29 @@ ij_status ij3_get_moments(ij3_sim *s, float *n_dev, float *phi_dev, float *ux_de
 ij_status ij3_get_state(ij3_sim *s, float *f_dev, float *g_dev, void *stream);
 ij_status ij3_set_state(ij3_sim *s, const float *f_dev, const float *g_dev, int64_t t, void *stream);
 
+/* Droplet segments of a sample (Results: breakup time and drop velocity,
+ * Figs. 3-4): the rows y >= row0 split into maximal runs of rows with ink;
+ * the run that starts at row0 is attached to the nozzle and every other run
+ * with at least a_min ink nodes is a detached drop. */
+typedef struct ij3_drops {
+    int64_t n_detached;        /* detached drops */
+    int64_t largest_count;     /* ink nodes (phi > 0) of the largest (the lowest on a tie) */
+    double largest_uy;         /* sum of u_y over them */
+    int64_t largest_top;       /* its highest row (-1: none) */
+    int64_t largest_bottom;    /* its lowest row (-1: none) */
+    double head_uy, tail_uy;   /* mean u_y of its ink in its top / bottom `band` rows */
+} ij3_drops;
+
 /* Diagnostic sums of the current state (Results: mass, momentum, breakup):
  * rec (host, 7 doubles) = {sum n, sum phi, sum c_x f, sum c_y f, sum c_z f,
  * max |u|, fluid nodes with a non-finite n, phi or u}; for each row y
  * (an x-z slice) with y >= row0, row_count[y] (host int64) = fluid nodes
  * with phi > 0 and row_uy[y] (host double) = the sum of their u_y (0 below
- * row0; either pointer may be NULL).  Sums accumulate in double in a fixed
- * order.  Synchronises the stream. */
-ij_status ij3_sample(ij3_sim *s, int64_t row0, double *rec, int64_t *row_count, double *row_uy, void *stream);
+ * row0; either pointer may be NULL).  With drops (host, may be NULL) the
+ * droplet segments of the sample, for a_min >= 1 and band >= 1.  Sums
+ * accumulate in double in a fixed order.  Synchronises the stream. */
+ij_status ij3_sample(ij3_sim *s, int64_t row0, double *rec, int64_t *row_count, double *row_uy, int64_t a_min,
+                     int64_t band, ij3_drops *drops, void *stream);
 
 #ifdef __cplusplus
 }

@@ -497,6 +497,64 @@ __global__ __launch_bounds__(DT) void k3_rows(K3 P, const float* __restrict__ A,
     if (threadIdx.x == 0) rows[y] = s[0];
 }
 
+// Droplet segments of a sample (Results: breakup, drop velocity): the rows
+// y >= row0 split into maximal runs with ink; the run that starts at row0 is
+// attached to the nozzle, every other run with at least a_min ink nodes is
+// a detached drop.  For the largest (the lowest on a tie): its ink count,
+// summed u_y, lowest and highest rows, and the mean u_y of its ink in its
+// top and bottom `band` rows (head and tail).  One thread, rows in order.
+__global__ void k3_drops(const Row3* __restrict__ rows, int ny, int row0, double a_min, int band,
+                         ij3_drops* __restrict__ out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int64_t n_det = 0;
+    int ba = -1, bb = -1;
+    double bc = 0.0, bu = 0.0;
+    int y = row0;
+    while (y < ny) {
+        if (!(rows[y].ink > 0.0)) {
+            ++y;
+            continue;
+        }
+        const int a = y;
+        double c = 0.0, u = 0.0;
+        while (y < ny && rows[y].ink > 0.0) {
+            c += rows[y].ink;
+            u += rows[y].uy;
+            ++y;
+        }
+        if (a != row0 && c >= a_min) {
+            ++n_det;
+            if (c > bc) {
+                bc = c;
+                bu = u;
+                ba = a;
+                bb = y;
+            }
+        }
+    }
+    ij3_drops d{};
+    d.n_detached = n_det;
+    d.largest_count = (int64_t)bc;
+    d.largest_uy = bu;
+    d.largest_bottom = ba;
+    d.largest_top = ba >= 0 ? bb - 1 : -1;
+    if (ba >= 0) {
+        double hc = 0.0, hu = 0.0, tc = 0.0, tu = 0.0;
+        for (int r = max(ba, bb - band); r < bb; ++r) {
+            hc += rows[r].ink;
+            hu += rows[r].uy;
+        }
+        for (int r = ba; r < min(bb, ba + band); ++r) {
+            tc += rows[r].ink;
+            tu += rows[r].uy;
+        }
+        d.head_uy = hu / hc;
+        d.tail_uy = tu / tc;
+    }
+    *out = d;
+}
+
 // totals over the rows, summed in row order by one thread
 __global__ void k3_finish(const Row3* __restrict__ rows, int ny, double* __restrict__ rec)
 {
@@ -529,6 +587,7 @@ struct ij3_sim {
     int n_ghost = 0;
     Row3* rows = nullptr;
     double* rec = nullptr;     // 7 totals of the last sample
+    ij3_drops* drops = nullptr;
     int cur = 0;
     int64_t t = 0;
     bool ready = false;
@@ -683,6 +742,7 @@ ij_status ij3_create(const ij3_params* p, const uint8_t* wall, ij3_sim** out)
         hipMalloc(&s->wall, K.plane) != hipSuccess || hipMalloc(&s->phi, K.plane * sizeof(double)) != hipSuccess ||
         hipMalloc(&s->rows, (size_t)ny * sizeof(Row3)) != hipSuccess ||
         hipMalloc(&s->rec, 7 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&s->drops, sizeof(ij3_drops)) != hipSuccess ||
         (s->n_ghost && hipMalloc(&s->ghost, gl.size() * sizeof(int4)) != hipSuccess))
         return cleanup(IJ_ERR_OOM, "device allocation failed");
     if (hipMemcpy(s->wall, wp.data(), K.plane, hipMemcpyHostToDevice) != hipSuccess ||
@@ -704,6 +764,7 @@ void ij3_destroy(ij3_sim* s)
     (void)hipFree(s->ghost);
     (void)hipFree(s->rows);
     (void)hipFree(s->rec);
+    (void)hipFree(s->drops);
     delete s;
 }
 
@@ -819,11 +880,13 @@ ij_status ij3_set_state(ij3_sim* s, const float* f, const float* g, int64_t t, v
     return IJ_OK;
 }
 
-ij_status ij3_sample(ij3_sim* s, int64_t row0, double* rec, int64_t* row_count, double* row_uy, void* stream)
+ij_status ij3_sample(ij3_sim* s, int64_t row0, double* rec, int64_t* row_count, double* row_uy, int64_t a_min,
+                     int64_t band, ij3_drops* drops, void* stream)
 {
     if (!s) return fail(nullptr, IJ_ERR_INVALID_ARG, "handle is NULL");
     if (!s->ready) return fail(s, IJ_ERR_STATE, "no state yet");
     if (!rec) return fail(s, IJ_ERR_INVALID_ARG, "rec is NULL");
+    if (drops && (a_min < 1 || band < 1)) return fail(s, IJ_ERR_INVALID_ARG, "a_min and band must be >= 1");
     hipStream_t st = (hipStream_t)stream;
     if (ij_status e = refresh_phi(s, st)) return e;
     const K3& K = s->K;
@@ -831,10 +894,14 @@ ij_status ij3_sample(ij3_sim* s, int64_t row0, double* rec, int64_t* row_count, 
     hipLaunchKernelGGL(k3_rows, dim3(K.ny), dim3(DT), 0, st, K, s->buf[s->cur], s->wall, s->phi,
                        (float)pulse(s->p, s->t), r0, s->rows);
     hipLaunchKernelGGL(k3_finish, dim3(1), dim3(64), 0, st, s->rows, K.ny, s->rec);
+    if (drops)
+        hipLaunchKernelGGL(k3_drops, dim3(1), dim3(64), 0, st, s->rows, K.ny, r0, (double)a_min,
+                           (int)std::min<int64_t>(band, K.ny), s->drops);
     IJ3_HIP(s, hipGetLastError());
     std::vector<Row3> h(K.ny);
     IJ3_HIP(s, hipMemcpyAsync(h.data(), s->rows, h.size() * sizeof(Row3), hipMemcpyDeviceToHost, st));
     IJ3_HIP(s, hipMemcpyAsync(rec, s->rec, 7 * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (drops) IJ3_HIP(s, hipMemcpyAsync(drops, s->drops, sizeof(ij3_drops), hipMemcpyDeviceToHost, st));
     IJ3_HIP(s, hipStreamSynchronize(st));
     for (int y = 0; y < K.ny; ++y) {
         if (row_count) row_count[y] = (int64_t)h[y].ink;

@@ -76,6 +76,12 @@ class IJ3Params(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in _INT3] + [(k, ctypes.c_double) for k in _DBL3]
 
 
+class IJ3Drops(ctypes.Structure):
+    _fields_ = [("n_detached", ctypes.c_int64), ("largest_count", ctypes.c_int64), ("largest_uy", ctypes.c_double),
+                ("largest_top", ctypes.c_int64), ("largest_bottom", ctypes.c_int64), ("head_uy", ctypes.c_double),
+                ("tail_uy", ctypes.c_double)]
+
+
 def load(path: str = LIB_PATH):
     """Load the HIP library (raises if it has not been built)."""
     global _lib
@@ -146,7 +152,7 @@ def load(path: str = LIB_PATH):
         "ij3_get_moments": (st, [vp, vp, vp, vp, vp, vp, vp]),
         "ij3_get_state": (st, [vp, vp, vp, vp]),
         "ij3_set_state": (st, [vp, vp, vp, i64, vp]),
-        "ij3_sample": (st, [vp, i64, vp, vp, vp, vp]),
+        "ij3_sample": (st, [vp, i64, vp, vp, vp, i64, i64, ctypes.POINTER(IJ3Drops), vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -8,11 +8,12 @@ pointers on torch's current stream.
 from __future__ import annotations
 
 import ctypes
+import math
 from typing import Optional
 
 import numpy as np
 
-from .lbm import IJ_OK, IJ3Params, LBMError, _INT3, _DBL3, _dptr, _stream_ptr, load
+from .lbm import IJ_OK, IJ3Drops, IJ3Params, LBMError, _INT3, _DBL3, _dptr, _stream_ptr, load
 
 Q, QG = 19, 7
 
@@ -113,12 +114,20 @@ class Sim3D:
         self._check(self.L.ij3_set_state(self.h, _dptr(ft), _dptr(gt), int(t), _stream_ptr(stream)))
         self._keep_state = (ft, gt)
 
-    def sample(self, row0: int = 0, stream=None) -> dict:
+    def sample(self, row0: int = 0, a_min: Optional[int] = None, band: Optional[int] = None, stream=None) -> dict:
+        """Sums, per-row ink profile and droplet segments of the current
+        state; a drop needs a_min ink nodes (default 4 W^3), head and tail
+        velocities average over `band` rows (default ceil(W))."""
+        w = float(self.params["width"])
+        a_min = int(round(4 * w ** 3)) if a_min is None else int(a_min)
+        band = int(math.ceil(w)) if band is None else int(band)
         rec = np.zeros(7)
         cnt = np.zeros(self.ny, dtype=np.int64)
         uy = np.zeros(self.ny)
+        d = IJ3Drops()
         self._check(self.L.ij3_sample(self.h, int(row0), rec.ctypes.data_as(ctypes.c_void_p),
                                       cnt.ctypes.data_as(ctypes.c_void_p), uy.ctypes.data_as(ctypes.c_void_p),
-                                      _stream_ptr(stream)))
+                                      a_min, band, ctypes.byref(d), _stream_ptr(stream)))
+        drops = {k: getattr(d, k) for k, _ in IJ3Drops._fields_}
         return dict(mass_n=rec[0], mass_phi=rec[1], mom=rec[2:5].copy(), max_u=rec[5], nan_count=int(rec[6]),
-                    row_count=cnt, row_uy=uy)
+                    row_count=cnt, row_uy=uy, drops=drops)

@@ -153,6 +153,15 @@ def test_diagnostics_match_oracle(oracle3d_mod, gpu_lib):
         assert np.all(s["row_count"][:row0] == 0)
         scale_u = np.abs(od["row_uy"]).max() + 1e-12
         assert np.all(np.abs(s["row_uy"] - od["row_uy"]) <= 1e-4 * scale_u + 1e-7 * od["row_count"])
+        # the device's droplet segments are the oracle's segments of the same rows
+        from oracle.oracle import segments
+        a_min = int(round(4 * c["params"]["width"] ** 3))
+        want = segments(s["row_count"], s["row_uy"], row0, a_min, band=4)
+        got = s["drops"]
+        for k in ("n_detached", "largest_count", "largest_top", "largest_bottom"):
+            assert got[k] == want[k], (k, got, want)
+        for k in ("largest_uy", "head_uy", "tail_uy"):
+            assert got[k] == pytest.approx(want[k], rel=1e-12, abs=1e-15), (k, got, want)
 
 
 def test_closed_box_conserves_mass(gpu_lib):
@@ -322,10 +331,13 @@ def test_round_nozzle_ejects_ink(gpu_lib):
         g.step(500)
         s = g.sample(c["row0"])
         assert s["nan_count"] == 0 and s["max_u"] < 0.2, (g.t, s["max_u"])
-        seg = segments(s["row_count"], s["row_uy"], c["row0"], 4 * c["params"]["width"] ** 3)
-        if seg["n_detached"] and first is None:
+        seg = segments(s["row_count"], s["row_uy"], c["row0"], int(round(4 * c["params"]["width"] ** 3)), band=4)
+        d = s["drops"]
+        assert d["n_detached"] == seg["n_detached"] and d["largest_count"] == seg["largest_count"], (d, seg)
+        assert d["largest_top"] == seg["largest_top"] and d["largest_bottom"] == seg["largest_bottom"]
+        if d["n_detached"] and first is None:
             first = g.t
-            print("detached at", first, "ink nodes", seg["largest_count"], flush=True)
+            print("detached at", first, "drop", d, flush=True)
     assert first is not None and 12000 <= first <= 18000, first
 
 
