@@ -194,7 +194,22 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
 {
     __shared__ double s_phi[HN];
     __shared__ uint8_t s_w[HN];
-    const int x0 = blockIdx.x * BX, z0 = blockIdx.y * BZ, y = blockIdx.z;
+    int bx = blockIdx.x, bz = blockIdx.y, y = blockIdx.z;
+    {
+        // workgroups b and b + 8 (one XCD, one after the other) take the two
+        // tiles of an x-pair, so the x-halo lines they share meet in one L2
+        const unsigned nxt = gridDim.x, nzt = gridDim.y;
+        const unsigned b = blockIdx.x + nxt * (blockIdx.y + nzt * blockIdx.z);
+        const unsigned total = nxt * nzt * gridDim.z;
+        if (nxt == 2 && (total & 15) == 0) {
+            const unsigned t = (b >> 4) * 16 + (b & 7) * 2 + ((b >> 3) & 1);
+            bx = (int)(t % nxt);
+            const unsigned r = t / nxt;
+            bz = (int)(r % nzt);
+            y = (int)(r / nzt);
+        }
+    }
+    const int x0 = bx * BX, z0 = bz * BZ;
     const int tid = threadIdx.y * BX + threadIdx.x;
     for (int e = tid; e < HN; e += BX * BZ) {
         const int dy = e / (HZ * HX), r = e - dy * (HZ * HX), ez = r / HX, ex = r - ez * HX;
