@@ -214,6 +214,11 @@ def test_errors(gpu_lib):
     with pytest.raises(lbm.LBMError) as e:
         lbm3d.Sim3D(p, bad)
     assert e.value.code == lbm.IJ_ERR_INVALID_ARG
+    g.init_distance(d)
+    for kw in (dict(a_min=0), dict(band=0)):
+        with pytest.raises(lbm.LBMError) as e:
+            g.sample(0, **kw)
+        assert e.value.code == lbm.IJ_ERR_INVALID_ARG
 
 
 def _window_compare(O3, p_full, wall, d, g_mom, y0, z0, x0, h, dz, dx, k, bc_y):
