@@ -46,7 +46,7 @@ typedef enum {
     IJ_ERR_INVALID_ARG = -1, /* bad parameter, size or geometry; nothing changed */
     IJ_ERR_OOM = -2,         /* device allocation failed */
     IJ_ERR_DEVICE = -3,      /* a HIP call failed (message has the HIP error) */
-    IJ_ERR_UNSTABLE = -4,    /* a diagnostics sample saw NaN or |u| > u_limit */
+    IJ_ERR_UNSTABLE = -4,    /* a diagnostics sample saw NaN, n <= 0 or |u| > u_limit */
     IJ_ERR_STATE = -5        /* call out of order (e.g. step before init) */
 } ij_status;
 
@@ -81,7 +81,8 @@ typedef struct ij_sample {
     double mass_n, mass_phi;   /* sum of n and of phi over fluid nodes */
     double mom_x, mom_y;       /* sum over fluid nodes of sum_i c_i f_i */
     double max_u;              /* max |u| over fluid nodes */
-    int64_t nan_count;         /* fluid nodes with a non-finite n, phi or u */
+    int64_t nan_count;         /* fluid nodes with a non-finite n, phi or u, or
+                                  with n <= 0 (the stability guard's count) */
     int64_t n_detached;        /* detached ink segments (rows >= diag_row0) */
     int64_t largest_count;     /* ink nodes (phi > 0) of the largest one */
     double largest_uy;         /* sum of u_y over those nodes */
@@ -185,8 +186,25 @@ ij_status ij_get_state(ij_sim *s, float *f_dev, float *g_dev, void *stream);
 ij_status ij_set_state(ij_sim *s, const float *f_dev, const float *g_dev, int64_t t,
                        void *stream);
 
+/* Checkpoint and bit-exact resume of the state the update works on (Eqs. 3
+ * and 8 advance f and g alone; the pulse phase of Fig. 1 follows from the
+ * step counter).  The blob is a 64-byte header (magic "IJSTATE1", lattice
+ * size, row pitch, step counter, a hash of the wall mask, payload size)
+ * followed by the current distribution buffer exactly as the kernels store
+ * it: the shifted f planes, the g planes and the 16-bit remainder plane of
+ * g_0.  ij_state_bytes gives its size (64 + ij_required_bytes).
+ * ij_save_state writes it to caller host memory of at least that size.
+ * ij_load_state restores it into a handle with the same lattice size and
+ * wall mask (IJ_ERR_INVALID_ARG otherwise, nothing changed), sets the step
+ * counter, and clears the recorded diagnostics samples and the stability
+ * flag.  Steps after a load are bit for bit those of the run that saved.
+ * Both synchronise the stream; the blob may be reused on return. */
+ij_status ij_state_bytes(const ij_sim *s, size_t *bytes);
+ij_status ij_save_state(ij_sim *s, void *blob_host, size_t bytes, void *stream);
+ij_status ij_load_state(ij_sim *s, const void *blob_host, size_t bytes, void *stream);
+
 /* Record one diagnostics sample at the current step (asynchronous): sums of
- * n, phi and momentum, max |u|, non-finite count, and the per-row ink
+ * n, phi and momentum, max |u|, the guard's count of bad nodes, and the per-row ink
  * profile of rows >= diag_row0 split into segments. */
 ij_status ij_diag_sample(ij_sim *s, void *stream);
 
@@ -204,7 +222,8 @@ ij_status ij_get_samples(ij_sim *s, ij_sample *out_host, int64_t cap, int64_t *c
 ij_status ij_get_diagnostics(ij_sim *s, ij_diag *out, void *stream);
 
 /* Synchronise and check every sample recorded so far against the guard
- * (non-finite values or max |u| > u_limit): IJ_OK or IJ_ERR_UNSTABLE. */
+ * (non-finite values, a density n <= 0, or max |u| > u_limit): IJ_OK or
+ * IJ_ERR_UNSTABLE. */
 ij_status ij_check(ij_sim *s, void *stream);
 
 /* Derived constants: out[0..7] = phi*, n0, beta, kappa, q, inner and outer
@@ -396,7 +415,8 @@ typedef struct ij3_sim ij3_sim;
 
 /* Validate *p and allocate, on the current device, two distribution buffers
  * (26 floats per node: the 19 f and 7 g rows of each lattice row (y, z) are
- * stored one after the other, row pitch nx rounded up to 64), the
+ * stored one after the other, row pitch nx rounded up to 64; then a 16-bit
+ * plane with the low-order part of g_0), the
  * phi field (double) and the wall mask from `wall` (host, [ny][nz][nx]
  * bytes, IJ_FLUID / IJ_WALL_INNER / IJ_WALL_OUTER; NULL: all fluid).  With
  * open rows, a fluid node of row 0 (ny-1) must have fluid directly above
@@ -430,6 +450,16 @@ ij_status ij3_get_moments(ij3_sim *s, float *n_dev, float *phi_dev, float *ux_de
 ij_status ij3_get_state(ij3_sim *s, float *f_dev, float *g_dev, void *stream);
 ij_status ij3_set_state(ij3_sim *s, const float *f_dev, const float *g_dev, int64_t t, void *stream);
 
+/* Checkpoint and bit-exact resume, as ij_state_bytes / ij_save_state /
+ * ij_load_state for the three-dimensional lattice: a 64-byte header (magic
+ * "IJ3STAT1", lattice size, row pitch, step counter, wall hash, payload
+ * size) and the current buffer as stored (shifted f, g, the g_0 remainder
+ * plane).  A load needs the same lattice size and wall mask.  Both
+ * synchronise the stream. */
+ij_status ij3_state_bytes(const ij3_sim *s, size_t *bytes);
+ij_status ij3_save_state(ij3_sim *s, void *blob_host, size_t bytes, void *stream);
+ij_status ij3_load_state(ij3_sim *s, const void *blob_host, size_t bytes, void *stream);
+
 /* Droplet segments of a sample (Results: breakup time and drop velocity,
  * Figs. 3-4): the rows y >= row0 split into maximal runs of rows with ink;
  * the run that starts at row0 is attached to the nozzle and every other run
@@ -445,7 +475,7 @@ typedef struct ij3_drops {
 
 /* Diagnostic sums of the current state (Results: mass, momentum, breakup):
  * rec (host, 7 doubles) = {sum n, sum phi, sum c_x f, sum c_y f, sum c_z f,
- * max |u|, fluid nodes with a non-finite n, phi or u}; for each row y
+ * max |u|, fluid nodes with a non-finite n, phi or u or with n <= 0}; for each row y
  * (an x-z slice) with y >= row0, row_count[y] (host int64) = fluid nodes
  * with phi > 0 and row_uy[y] (host double) = the sum of their u_y (0 below
  * row0; either pointer may be NULL).  With drops (host, may be NULL) the

@@ -544,7 +544,8 @@ void o3_diag(o3_sim *s, long row0, double rec[7], int64_t *row_count, double *ro
                 sn += nd.n;
                 sp += nd.phi;
                 double um = sqrt(nd.u[0] * nd.u[0] + nd.u[1] * nd.u[1] + nd.u[2] * nd.u[2]);
-                if (!isfinite(nd.n) || !isfinite(nd.phi) || !isfinite(um))
+                /* non-finite, or a density that is not positive */
+                if (!isfinite(nd.n) || !isfinite(nd.phi) || !isfinite(um) || !(nd.n > 0.0))
                     bad += 1;
                 else if (um > umax)
                     umax = um;

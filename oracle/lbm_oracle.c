@@ -577,7 +577,9 @@ void o_diag(o_sim *s, long row0, double rec[6], int64_t *row_count, double *row_
             sjx += jx;
             sjy += jy;
             double um = sqrt(nd.ux * nd.ux + nd.uy * nd.uy);
-            if (!isfinite(nd.n) || !isfinite(nd.phi) || !isfinite(um))
+            /* the stability guard's count: a non-finite value, or a density
+             * that is not positive (n <= 0 has no meaning in Eq. 1) */
+            if (!isfinite(nd.n) || !isfinite(nd.phi) || !isfinite(um) || !(nd.n > 0.0))
                 bad += 1;
             else if (um > umax)
                 umax = um;

@@ -340,7 +340,13 @@ ij_status drain_samples(ij_sim* s, hipStream_t st)
         ij_sample o;
         std::memcpy(&o, &r, sizeof o);
         s->host_samples.push_back(o);
-        if (s->unstable_step < 0 && (o.nan_count > 0 || !(o.max_u <= u_limit(s->p)))) s->unstable_step = o.step;
+        if (s->unstable_step < 0 && (o.nan_count > 0 || !(o.max_u <= u_limit(s->p)))) {
+            s->unstable_step = o.step;
+            // A batch switches such a case off on the device at the same
+            // sample: its state stays in the buffer that was current at that
+            // step, while the host went on alternating its buffers.
+            if (s->in_batch) s->cur ^= (int)((s->t - o.step) & 1);
+        }
     }
     s->n_dev_samples = 0;
     return IJ_OK;
@@ -621,6 +627,10 @@ ij_status ij_get_moments(ij_sim* s, float* n, float* ph, float* ux, float* uy, v
     if (!s) return IJ_ERR_INVALID_ARG;
     if (!s->initialised) return fail(s, IJ_ERR_STATE, "moments before init");
     hipStream_t st = (hipStream_t)stream;
+    if (s->in_batch) {   // the buffer of a case the batch froze is known once its samples are read
+        const ij_status r = drain_samples(s, st);
+        if (r != IJ_OK) return r;
+    }
     s->K.fb = (float)pulse_value(s->p, s->t);
     hipError_t e = ij::launch_phi_ghost(s->K, s->buf[s->cur], s->wall, s->phi, s->ghost, s->n_ghost, st);
     if (e == hipSuccess) e = ij::launch_moments(s->K, s->buf[s->cur], s->wall, s->phi, n, ph, ux, uy, st);
@@ -632,6 +642,10 @@ ij_status ij_get_state(ij_sim* s, float* f, float* g, void* stream)
 {
     if (!s) return IJ_ERR_INVALID_ARG;
     if (!s->initialised) return fail(s, IJ_ERR_STATE, "state before init");
+    if (s->in_batch) {   // the buffer of a case the batch froze is known once its samples are read
+        const ij_status r = drain_samples(s, (hipStream_t)stream);
+        if (r != IJ_OK) return r;
+    }
     hipError_t e = ij::launch_state_io(s->K, s->buf[s->cur], s->wall, f, g, 1, (hipStream_t)stream);
     return e == hipSuccess ? IJ_OK : hip_fail(s, e, "state readback kernel");
 }
@@ -648,10 +662,74 @@ ij_status ij_set_state(ij_sim* s, const float* f, const float* g, int64_t t, voi
     return IJ_OK;
 }
 
+ij_status ij_state_bytes(const ij_sim* s, size_t* bytes)
+{
+    if (!s || !bytes) return IJ_ERR_INVALID_ARG;
+    *bytes = sizeof(StateHeader) + buffer_bytes(s->plane);
+    return IJ_OK;
+}
+
+ij_status ij_save_state(ij_sim* s, void* blob, size_t bytes, void* stream)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (!blob) return fail(s, IJ_ERR_INVALID_ARG, "blob is NULL");
+    if (!s->initialised) return fail(s, IJ_ERR_STATE, "state before init");
+    const size_t payload = buffer_bytes(s->plane);
+    if (bytes < sizeof(StateHeader) + payload) return fail(s, IJ_ERR_INVALID_ARG, "blob smaller than ij_state_bytes");
+    hipStream_t st = (hipStream_t)stream;
+    if (s->in_batch) {   // the buffer of a case the batch froze is known once its samples are read
+        const ij_status r = drain_samples(s, st);
+        if (r != IJ_OK) return r;
+    }
+    StateHeader h{};
+    std::memcpy(h.magic, "IJSTATE1", 8);
+    h.nx = s->nx;
+    h.ny = s->ny;
+    h.nz = 1;
+    h.pitch = s->pitch;
+    h.t = s->t;
+    h.wall_hash = fnv1a(s->wall_host.data(), s->wall_host.size());
+    h.payload = payload;
+    std::memcpy(blob, &h, sizeof h);
+    IJ_HIP(s, hipMemcpyAsync((char*)blob + sizeof h, s->buf[s->cur], payload, hipMemcpyDeviceToHost, st));
+    IJ_HIP(s, hipStreamSynchronize(st));
+    return IJ_OK;
+}
+
+ij_status ij_load_state(ij_sim* s, const void* blob, size_t bytes, void* stream)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (!blob || bytes < sizeof(StateHeader)) return fail(s, IJ_ERR_INVALID_ARG, "blob is NULL or too small");
+    StateHeader h;
+    std::memcpy(&h, blob, sizeof h);
+    const size_t payload = buffer_bytes(s->plane);
+    if (std::memcmp(h.magic, "IJSTATE1", 8) != 0) return fail(s, IJ_ERR_INVALID_ARG, "not a checkpoint of this library");
+    if (h.nx != s->nx || h.ny != s->ny || h.nz != 1 || h.pitch != s->pitch || h.payload != payload)
+        return fail(s, IJ_ERR_INVALID_ARG, "checkpoint of a different lattice size");
+    if (h.wall_hash != fnv1a(s->wall_host.data(), s->wall_host.size()))
+        return fail(s, IJ_ERR_INVALID_ARG, "checkpoint of a different wall mask");
+    if (h.t < 0) return fail(s, IJ_ERR_INVALID_ARG, "negative step counter");
+    if (bytes < sizeof h + payload) return fail(s, IJ_ERR_INVALID_ARG, "blob shorter than its payload");
+    hipStream_t st = (hipStream_t)stream;
+    IJ_HIP(s, hipMemcpyAsync(s->buf[0], (const char*)blob + sizeof h, payload, hipMemcpyHostToDevice, st));
+    IJ_HIP(s, hipStreamSynchronize(st));
+    s->cur = 0;
+    s->t = h.t;
+    s->initialised = true;
+    s->host_samples.clear();
+    s->n_dev_samples = 0;
+    s->unstable_step = -1;
+    return IJ_OK;
+}
+
 ij_status ij_diag_sample(ij_sim* s, void* stream)
 {
     if (!s) return IJ_ERR_INVALID_ARG;
     if (!s->initialised) return fail(s, IJ_ERR_STATE, "diagnostics before init");
+    if (s->in_batch) {
+        const ij_status r = drain_samples(s, (hipStream_t)stream);
+        if (r != IJ_OK) return r;
+    }
     return record_sample(s, (hipStream_t)stream);
 }
 

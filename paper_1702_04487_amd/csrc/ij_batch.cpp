@@ -187,11 +187,29 @@ ij_status build_tiles(ij_batch* b)
     return set_grids(b);
 }
 
+// Cases the device switched off since the host last looked are learnt from
+// their samples (which also tells which of a case's buffers holds its frozen
+// state).  Synchronises the stream.
+ij_status learn_frozen(ij_batch* b, hipStream_t st)
+{
+    IJB_HIP(b, hipEventSynchronize(b->staged));   // the previous uploads have been read
+    const size_t nc = b->sims.size();
+    IJB_HIP(b, hipStreamSynchronize(st));
+    IJB_HIP(b, hipMemcpy(b->h_active, b->d_active, nc * sizeof(int), hipMemcpyDeviceToHost));
+    for (size_t c = 0; c < nc; ++c) {
+        ij_sim* s = b->sims[c];
+        if (!b->h_active[c] && s->unstable_step < 0 && drain_samples(s, st) != IJ_OK)
+            return bfail(b, IJ_ERR_DEVICE, s->err);
+    }
+    return IJ_OK;
+}
+
 // Case records, sample counters and guard flags of the current state, on
 // the stream.  Relative parity 0 is each case's current buffer.
 ij_status stage(ij_batch* b, hipStream_t st)
 {
-    IJB_HIP(b, hipEventSynchronize(b->staged));   // the previous uploads have been read
+    const ij_status fr = learn_frozen(b, st);
+    if (fr != IJ_OK) return fr;
     for (size_t c = 0; c < b->sims.size(); ++c) {
         ij_sim* s = b->sims[c];
         ij::CaseRec& r = b->h_cases[c];
@@ -238,7 +256,8 @@ hipError_t one_step(ij_batch* b, int parity, bool diag, bool with_tick, hipStrea
                                   b->d_nrec, b->d_active, st);
     if (e == hipSuccess)
         e = ij::launch_batch_collide(b->T, b->d_cases, parity, b->d_t, b->d_active, b->waves_x, st);
-    if (e == hipSuccess && with_tick) e = ij::launch_batch_tick(b->d_t, st);
+    if (e == hipSuccess && with_tick)
+        e = ij::launch_batch_tick(b->d_t, b->d_cases, (int)b->sims.size(), b->d_active, st);
     return e;
 }
 
@@ -325,7 +344,9 @@ ij_status run_steps(ij_batch* b, int64_t n, hipStream_t st, bool use_graph)
     const int64_t ns = samples_in(b->t, n, b->diag_every);
     for (ij_sim* s : b->sims) {
         s->t = b->t + n;
-        if (n & 1) s->cur = 1 - s->cur;
+        // a case switched off before this call keeps its buffer (the device
+        // swaps its two buffers after every step instead)
+        if ((n & 1) && s->unstable_step < 0) s->cur = 1 - s->cur;
         s->n_dev_samples += ns;
     }
     b->t += n;
@@ -398,6 +419,7 @@ ij_status ij_batch_create(const ij_params* cases, int32_t n, ij_batch** out)
     if (hipMalloc(&b->d_cases, nb * sizeof(ij::CaseRec)) != hipSuccess ||
         hipMalloc(&b->d_t, sizeof(int64_t)) != hipSuccess || hipMalloc(&b->d_nrec, nb * sizeof(int64_t)) != hipSuccess ||
         hipMalloc(&b->d_active, nb * sizeof(int)) != hipSuccess ||
+        hipMemset(b->d_active, 0, nb * sizeof(int)) != hipSuccess ||
         hipHostMalloc(&b->h_cases, nb * sizeof(ij::CaseRec), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&b->h_nrec, nb * sizeof(int64_t), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(&b->h_active, nb * sizeof(int), hipHostMallocDefault) != hipSuccess)
@@ -536,6 +558,8 @@ ij_status ij_batch_autotune(ij_batch* b, int32_t trial_steps, void* stream, int3
         }
     }
     // keep the state: trial steps run on the live buffers and are undone
+    r = learn_frozen(b, st);   // each case's current buffer
+    if (r != IJ_OK) return r;
     std::vector<void*> saved(b->sims.size(), nullptr);
     auto release = [&]() {
         (void)hipStreamSynchronize(st);

@@ -6,10 +6,14 @@
 #include <string>
 #include <vector>
 
+#include "checkpoint.h"
 #include "inkjet_lbm.h"
 #include "lbm_core.h"
 
 namespace ij_host {
+
+using ij_ckpt::StateHeader;
+using ij_ckpt::fnv1a;
 
 constexpr int kPitchAlign = 64;    // floats: 256-byte rows
 constexpr int64_t kSampleCap = 4096;

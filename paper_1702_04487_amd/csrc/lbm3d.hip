@@ -7,14 +7,19 @@
 // "Reproducing the experiment", written on three-dimensional lattices.
 //
 // Storage: two buffers of 26 float populations per node (f_0..f_18, then
-// g_0..g_6).  The populations of one lattice row (fixed y, z) are 26
-// consecutive rows of pitch floats (nx rounded up to 64): population i of
-// node x of row r = y*nz + z sits at (r*26 + i)*pitch + x, so a workgroup's
-// 26 streams lie in one contiguous region of memory.  The wall mask and phi
-// are plain [y][z][pitch] arrays (node k = r*pitch + x).  f is
-// stored shifted by w_i n0 (the equilibrium of the mean density at rest), so
-// that float carries the deviations that the collision works on.  phi, its
-// wetting ghosts, the stencils and mu are double precision.
+// g_0..g_6) followed by one 16-bit plane.  The populations of one lattice
+// row (fixed y, z) are 26 consecutive rows of pitch floats (nx rounded up to
+// 64): population i of node x of row r = y*nz + z sits at (r*26 + i)*pitch +
+// x, so a workgroup's 26 streams lie in one contiguous region of memory.
+// The 16-bit plane, [y][z][pitch], holds the bfloat16 remainder of the rest
+// population g_0 - float(g_0): g_0 carries +-phi*, and its float rounding
+// alone, accumulated over the steps, would move phi and through mu the
+// velocity field by more than the float rounding of every other population
+// together.  The g_0 update is formed in double for the same reason.  The
+// wall mask and phi are plain [y][z][pitch] arrays (node k = r*pitch + x).
+// f is stored shifted by w_i n0 (the equilibrium of the mean density at
+// rest), so that float carries the deviations that the collision works on.
+// phi, its wetting ghosts, the stencils and mu are double precision.
 //
 // One step is two launches: the ghost phi of the solid nodes within reach of
 // fluid (from their fluid neighbours' g), and one collide-and-push launch
@@ -35,9 +40,14 @@
 #include <string>
 #include <vector>
 
+#include "bf16_split.h"
+#include "checkpoint.h"
 #include "inkjet_lbm.h"
 
 namespace ij3 {
+
+using ij_bf16::bf16_to_float;
+using ij_bf16::split;
 
 constexpr int Q = 19, QG = 7, NPL = Q + QG;
 constexpr int CX[Q] = {0, 1, 0, -1, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1, 0, 0, 0, 0};
@@ -54,7 +64,7 @@ struct K3 {
     int nx, ny, nz, pitch;
     size_t plane;     // nodes, row padding included: ny * nz * pitch
     int bc_open, force_rows;
-    double phi_star, n0, beta4, kappa, q;
+    double phi_star, n0, beta4, kappa, q, inv_tau_phid, gammad;
     double wet[3];    // ghost offsets 2 Omega phi* / W of wall classes 1, 2
     float omq, inv_tau_phi, gamma, inv_2q, tau_ink, tau_amb, n0f, inv_phi_star;
 };
@@ -69,6 +79,15 @@ __device__ __forceinline__ size_t nodek(const K3& P, int x, int y, int z)
 {
     return ((size_t)y * P.nz + z) * P.pitch + x;
 }
+// the g_0 remainder plane of a buffer, indexed by node k
+__device__ __forceinline__ const uint16_t* lo3(const K3& P, const float* A)
+{
+    return reinterpret_cast<const uint16_t*>(A + (size_t)NPL * P.plane);
+}
+__device__ __forceinline__ uint16_t* lo3(const K3& P, float* A)
+{
+    return reinterpret_cast<uint16_t*>(A + (size_t)NPL * P.plane);
+}
 
 // row of a stencil neighbour: periodic, or mirrored onto the open row
 __device__ __forceinline__ int stencil_row(const K3& P, int y)
@@ -76,6 +95,16 @@ __device__ __forceinline__ int stencil_row(const K3& P, int y)
     if (y >= 0 && y < P.ny) return y;
     if (P.bc_open) return y < 0 ? 0 : P.ny - 1;
     return wrapi(y, P.ny);
+}
+
+// phi = sum g of a fluid node (Eq. 9's zeroth moment), in double, with the
+// remainder of g_0; every kernel that needs phi of a node forms it here
+__device__ __forceinline__ double phi_of_g(const K3& P, const float* __restrict__ A, size_t k, int x)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int i = 1; i < QG; ++i) s += (double)A[pidx(P, k, x, Q + i)];
+    return (s + (double)bf16_to_float(lo3(P, A)[k])) + (double)A[pidx(P, k, x, Q)];
 }
 
 // phi = sum_i g_i at fluid nodes
@@ -86,10 +115,7 @@ __global__ __launch_bounds__(BX* BZ) void k3_phi(K3 P, const float* __restrict__
     if (x >= P.nx || z >= P.nz) return;
     const size_t k = nodek(P, x, y, z);
     if (wall[k]) return;
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < QG; ++i) s += (double)A[pidx(P, k, x, Q + i)];
-    phi[k] = s;
+    phi[k] = phi_of_g(P, A, k, x);
 }
 
 // ghost phi of each listed solid node (x, y, z, wall class): the mean of its
@@ -117,15 +143,6 @@ __global__ void k3_ghost(K3 P, const int4* __restrict__ list, int n, const uint8
         }
     }
     phi[nodek(P, L.x, L.y, L.z)] = cnt ? sum / cnt + P.wet[L.w] : 0.0;
-}
-
-// phi = sum g of a fluid node, summed in the order of k3_phi
-__device__ __forceinline__ double phi_of_g(const K3& P, const float* __restrict__ A, size_t k, int x)
-{
-    double s = 0.0;
-#pragma unroll
-    for (int i = 0; i < QG; ++i) s += (double)A[pidx(P, k, x, Q + i)];
-    return s;
 }
 
 // the ghost of each listed solid node as k3_ghost computes it, with the
@@ -266,7 +283,9 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
     }
     const float n = P.n0f + dn;
     const float inv_n = 1.f / n;
-    const float ux = (jx + 0.5f * fx) * inv_n, uy = (jy + 0.5f * fy) * inv_n, uz = (jz + 0.5f * fz) * inv_n;
+    // j and -F/2 nearly cancel at a resting interface: add them in double
+    const float ux = (float)((double)jx + 0.5 * Fx) * inv_n, uy = (float)((double)jy + 0.5 * Fy) * inv_n,
+                uz = (float)((double)jz + 0.5 * Fz) * inv_n;
     const float phif = (float)ph.phi;
     float C = (phif * P.inv_phi_star + 1.f) * 0.5f;
     C = fminf(fmaxf(C, 0.f), 1.f);
@@ -303,18 +322,29 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
     }
 
     // g: equilibrium of Eqs. 9-10 on D3Q7, h = g* - (1-q) g, and the
-    // destination keeps (1-q) of its own old value (Eq. 8)
+    // destination keeps (1-q) of its own old value (Eq. 8).  The rest
+    // population stays: its new value h_0 + (1-q) g_0 = g_0 + (g_eq_0 -
+    // g_0)/tau_phi, with g_eq_0 - g_0 = (g_1 + .. + g_6) - 3 Gamma mu, is
+    // formed in double and stored as float plus remainder.
+    {
+        double sg = 0.0;
+#pragma unroll
+        for (int i = 1; i < QG; ++i) sg += (double)g[i];
+        const double G = ((double)g[0] + (double)bf16_to_float(lo3(P, A)[k])) +
+                         P.inv_tau_phid * (sg - 3.0 * P.gammad * ph.mu);
+        float hi;
+        uint16_t lo;
+        split(G, hi, lo);
+        B[pidx(P, k, x, Q)] = hi;
+        lo3(P, B)[k] = lo;
+    }
     const float gmu = P.gamma * (float)ph.mu;
 #pragma unroll
-    for (int i = 0; i < QG; ++i) {
+    for (int i = 1; i < QG; ++i) {
         const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-        const float geq = i == 0 ? phif - 3.f * gmu : 0.5f * gmu + phif * cu * P.inv_2q;
+        const float geq = 0.5f * gmu + phif * cu * P.inv_2q;
         const float gs = g[i] + (geq - g[i]) * P.inv_tau_phi;
         const float h = gs - P.omq * g[i];
-        if (i == 0) {
-            B[pidx(P, k, x, Q)] = h + P.omq * g[0];
-            continue;
-        }
         const uint8_t wd = s_w[lds(i)];
         if (wd == kBeyond) continue;
         if (wd) {
@@ -367,6 +397,7 @@ __global__ void k3_init_eq(K3 P, float* __restrict__ A, const uint8_t* __restric
     const size_t k = nodek(P, x, y, z);
     if (wall[k]) {
         for (int i = 0; i < NPL; ++i) A[pidx(P, k, x, i)] = 0.f;
+        lo3(P, A)[k] = 0;
         return;
     }
     const size_t ke = ((size_t)y * P.nz + z) * P.nx + x;
@@ -380,10 +411,15 @@ __global__ void k3_init_eq(K3 P, float* __restrict__ A, const uint8_t* __restric
         A[pidx(P, k, x, i)] = wt(i) * (a + n * (3.f * cu + 4.5f * cu * cu - 1.5f * uu));
     }
     const float gmu = P.gamma * (float)ph.mu, phif = (float)ph.phi;
+    float g0;
+    uint16_t g0lo;
+    split(ph.phi - 3.0 * P.gammad * ph.mu, g0, g0lo);
+    A[pidx(P, k, x, Q)] = g0;
+    lo3(P, A)[k] = g0lo;
 #pragma unroll
-    for (int i = 0; i < QG; ++i) {
+    for (int i = 1; i < QG; ++i) {
         const float cu = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
-        A[pidx(P, k, x, Q + i)] = i == 0 ? phif - 3.f * gmu : 0.5f * gmu + phif * cu * P.inv_2q;
+        A[pidx(P, k, x, Q + i)] = 0.5f * gmu + phif * cu * P.inv_2q;
     }
 }
 
@@ -410,9 +446,10 @@ __device__ __forceinline__ Mac3 node_macro(const K3& P, const float* __restrict_
     Mac3 m;
     m.n = P.n0f + dn;
     m.phi = (float)ph.phi;
-    m.ux = (jx + 0.5f * (float)Fx) / m.n;
-    m.uy = (jy + 0.5f * (float)Fy) / m.n;
-    m.uz = (jz + 0.5f * (float)Fz) / m.n;
+    const float inv_n = 1.f / m.n;
+    m.ux = (float)((double)jx + 0.5 * Fx) * inv_n;
+    m.uy = (float)((double)jy + 0.5 * Fy) * inv_n;
+    m.uz = (float)((double)jz + 0.5 * Fz) * inv_n;
     m.jx = jx;
     m.jy = jy;
     m.jz = jz;
@@ -437,7 +474,8 @@ __global__ void k3_moments(K3 P, const float* __restrict__ A, const uint8_t* __r
 }
 
 // distributions <-> caller arrays [i][ny][nz][nx]: the f planes (is_f, the
-// stored shift removed) or the g planes
+// stored shift removed) or the g planes (g_0 read as float(hi + remainder);
+// writing g_0 clears its remainder)
 __global__ void k3_state_io(K3 P, float* __restrict__ A, const uint8_t* __restrict__ wall,
                             float* __restrict__ ext, int to_ext, int is_f)
 {
@@ -451,10 +489,15 @@ __global__ void k3_state_io(K3 P, float* __restrict__ A, const uint8_t* __restri
     for (int i = 0; i < nq; ++i) {
         const float shift = is_f ? wt(i) * P.n0f : 0.f;
         const size_t pk = pidx(P, k, x, i0 + i);
+        const bool rest_g = !is_f && i == 0;
         if (to_ext)
-            ext[i * ne + ke] = solid ? 0.f : A[pk] + shift;
-        else if (!solid)
+            ext[i * ne + ke] = solid ? 0.f
+                                     : (rest_g ? (float)((double)A[pk] + (double)bf16_to_float(lo3(P, A)[k]))
+                                               : A[pk] + shift);
+        else if (!solid) {
             A[pk] = ext[i * ne + ke] - shift;
+            if (rest_g) lo3(P, A)[k] = 0;
+        }
     }
 }
 
@@ -481,7 +524,7 @@ __global__ __launch_bounds__(DT) void k3_rows(K3 P, const float* __restrict__ A,
         a.jy += (double)m.jy;
         a.jz += (double)m.jz;
         const float um = sqrtf(m.ux * m.ux + m.uy * m.uy + m.uz * m.uz);
-        if (!isfinite(m.n) || !isfinite(m.phi) || !isfinite(um))
+        if (!isfinite(m.n) || !isfinite(m.phi) || !isfinite(um) || !(m.n > 0.f))
             a.bad += 1.0;
         else
             a.umax = fmax(a.umax, (double)um);
@@ -606,6 +649,7 @@ struct ij3_sim {
     int cur = 0;
     int64_t t = 0;
     bool ready = false;
+    uint64_t wall_hash = 0;   // of the host wall mask [ny][nz][nx]
     std::string err;
 };
 
@@ -651,6 +695,10 @@ double pulse(const ij3_params& p, int64_t t)
     if (tt < p.t_pos + p.t_neg) return -p.f_neg;
     return 0.0;
 }
+
+// one distribution buffer: 26 float populations per node and the 16-bit g_0
+// remainder plane
+size_t buffer_bytes3(const K3& K) { return K.plane * (NPL * sizeof(float) + sizeof(uint16_t)); }
 
 dim3 grid_of(const K3& K, int zdim) { return dim3((K.nx + BX - 1) / BX, (K.nz + BZ - 1) / BZ, zdim); }
 
@@ -699,6 +747,7 @@ ij_status ij3_create(const ij3_params* p, const uint8_t* wall, ij3_sim** out)
 
     ij3_sim* s = new ij3_sim();
     s->p = *p;
+    s->wall_hash = ij_ckpt::fnv1a(w.data(), w.size());
     K3& K = s->K;
     K.nx = nx;
     K.ny = ny;
@@ -716,6 +765,8 @@ ij_status ij3_create(const ij3_params* p, const uint8_t* wall, ij3_sim** out)
     K.wet[0] = 0.0;
     K.wet[1] = 2.0 * omega_of_theta(p->theta_inner) * K.phi_star / p->width;
     K.wet[2] = 2.0 * omega_of_theta(p->theta_outer) * K.phi_star / p->width;
+    K.inv_tau_phid = 1.0 / p->tau_phi;
+    K.gammad = p->gamma;
     K.omq = (float)(1.0 - K.q);
     K.inv_tau_phi = (float)(1.0 / p->tau_phi);
     K.gamma = (float)p->gamma;
@@ -744,7 +795,7 @@ ij_status ij3_create(const ij3_params* p, const uint8_t* wall, ij3_sim** out)
             }
     s->n_ghost = (int)gl.size();
 
-    const size_t bytes = K.plane * NPL * sizeof(float);
+    const size_t bytes = buffer_bytes3(K);
     std::vector<uint8_t> wp(K.plane, 1);   // pitch padding reads as solid
     for (int y = 0; y < ny; ++y)
         for (int z = 0; z < nz; ++z)
@@ -882,7 +933,7 @@ ij_status ij3_set_state(ij3_sim* s, const float* f, const float* g, int64_t t, v
     if (!f || !g || t < 0) return fail(s, IJ_ERR_INVALID_ARG, "f and g are required, t >= 0");
     const K3& K = s->K;
     hipStream_t st = (hipStream_t)stream;
-    const size_t bytes = K.plane * NPL * sizeof(float);
+    const size_t bytes = buffer_bytes3(K);
     IJ3_HIP(s, hipMemsetAsync(s->buf[0], 0, bytes, st));
     hipLaunchKernelGGL(k3_state_io, grid_of(K, K.ny), dim3(BX, BZ), 0, st, K, s->buf[0], s->wall,
                        const_cast<float*>(f), 0, 1);
@@ -891,6 +942,61 @@ ij_status ij3_set_state(ij3_sim* s, const float* f, const float* g, int64_t t, v
     IJ3_HIP(s, hipGetLastError());
     s->cur = 0;
     s->t = t;
+    s->ready = true;
+    return IJ_OK;
+}
+
+ij_status ij3_state_bytes(const ij3_sim* s, size_t* bytes)
+{
+    if (!s || !bytes) return IJ_ERR_INVALID_ARG;
+    *bytes = sizeof(ij_ckpt::StateHeader) + buffer_bytes3(s->K);
+    return IJ_OK;
+}
+
+ij_status ij3_save_state(ij3_sim* s, void* blob, size_t bytes, void* stream)
+{
+    if (!s) return fail(nullptr, IJ_ERR_INVALID_ARG, "handle is NULL");
+    if (!blob) return fail(s, IJ_ERR_INVALID_ARG, "blob is NULL");
+    if (!s->ready) return fail(s, IJ_ERR_STATE, "no state yet");
+    const K3& K = s->K;
+    const size_t payload = buffer_bytes3(K);
+    if (bytes < sizeof(ij_ckpt::StateHeader) + payload)
+        return fail(s, IJ_ERR_INVALID_ARG, "blob smaller than ij3_state_bytes");
+    ij_ckpt::StateHeader h{};
+    std::memcpy(h.magic, "IJ3STAT1", 8);
+    h.nx = K.nx;
+    h.ny = K.ny;
+    h.nz = K.nz;
+    h.pitch = K.pitch;
+    h.t = s->t;
+    h.wall_hash = s->wall_hash;
+    h.payload = payload;
+    std::memcpy(blob, &h, sizeof h);
+    hipStream_t st = (hipStream_t)stream;
+    IJ3_HIP(s, hipMemcpyAsync((char*)blob + sizeof h, s->buf[s->cur], payload, hipMemcpyDeviceToHost, st));
+    IJ3_HIP(s, hipStreamSynchronize(st));
+    return IJ_OK;
+}
+
+ij_status ij3_load_state(ij3_sim* s, const void* blob, size_t bytes, void* stream)
+{
+    if (!s) return fail(nullptr, IJ_ERR_INVALID_ARG, "handle is NULL");
+    if (!blob || bytes < sizeof(ij_ckpt::StateHeader)) return fail(s, IJ_ERR_INVALID_ARG, "blob is NULL or too small");
+    ij_ckpt::StateHeader h;
+    std::memcpy(&h, blob, sizeof h);
+    const K3& K = s->K;
+    const size_t payload = buffer_bytes3(K);
+    if (std::memcmp(h.magic, "IJ3STAT1", 8) != 0) return fail(s, IJ_ERR_INVALID_ARG, "not a 3-D checkpoint of this library");
+    if (h.nx != K.nx || h.ny != K.ny || h.nz != K.nz || h.pitch != K.pitch || h.payload != payload)
+        return fail(s, IJ_ERR_INVALID_ARG, "checkpoint of a different lattice size");
+    if (h.wall_hash != s->wall_hash) return fail(s, IJ_ERR_INVALID_ARG, "checkpoint of a different wall mask");
+    if (h.t < 0) return fail(s, IJ_ERR_INVALID_ARG, "negative step counter");
+    if (bytes < sizeof h + payload) return fail(s, IJ_ERR_INVALID_ARG, "blob shorter than its payload");
+    hipStream_t st = (hipStream_t)stream;
+    IJ3_HIP(s, hipMemcpyAsync(s->buf[0], (const char*)blob + sizeof h, payload, hipMemcpyHostToDevice, st));
+    IJ3_HIP(s, hipStreamSynchronize(st));
+    s->cur = 0;
+    s->t = h.t;
     s->ready = true;
     return IJ_OK;
 }

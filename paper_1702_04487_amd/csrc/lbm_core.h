@@ -109,7 +109,9 @@ struct BatchTiles {
 };
 hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int64_t* t_dev,
                                 const int* active, int waves_x, hipStream_t st);
-hipError_t launch_batch_tick(int64_t* t_dev, hipStream_t st);
+// advances the step counter; a case switched off has its two buffers swapped,
+// so that the buffer a step reads is always the one that holds its state
+hipError_t launch_batch_tick(int64_t* t_dev, CaseRec* cases, int n_cases, const int* active, hipStream_t st);
 hipError_t launch_batch_set_time(int64_t* t_dev, int64_t t, hipStream_t st);
 hipError_t launch_batch_diag(const CaseRec* cases, int n_cases, int max_nx, int max_ny, int max_ghost, int parity,
                              const int64_t* t_dev, int64_t* n_rec, int* active, hipStream_t st);

@@ -23,21 +23,15 @@
 
 #include <algorithm>
 
+#include "bf16_split.h"
 #include "lbm_core.h"
 
 namespace ij {
 
 // ---------------------------------------------------------------- device math
 
-__device__ __forceinline__ float bf16_to_float(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
-// round-to-nearest-even to bfloat16 (finite inputs)
-__device__ __forceinline__ uint16_t float_to_bf16(float x)
-{
-    uint32_t u = __float_as_uint(x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+using ij_bf16::bf16_to_float;
+using ij_bf16::float_to_bf16;
 
 // phi = sum_i g_i (Eq. 9's zeroth moment) in double from the five stored
 // populations and the low-order part of g_0
@@ -533,7 +527,9 @@ __device__ __forceinline__ void sample_node(const Macro& m, bool ink_row, Sample
     d.jx = (double)m.jx;
     d.jy = (double)m.jy;
     const float um = sqrtf(m.ux * m.ux + m.uy * m.uy);
-    if (!isfinite(m.n) || !isfinite(m.phi) || !isfinite(um))
+    // the guard's count: a non-finite value, or a density that is not
+    // positive (the mean density n of Eq. 1 must stay above zero)
+    if (!isfinite(m.n) || !isfinite(m.phi) || !isfinite(um) || !(m.n > 0.f))
         d.bad = 1;
     else
         d.u = um;
@@ -874,7 +870,14 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
 #pragma unroll
             for (int i = 0; i < 9; ++i) rf[S][i] = ldf(Af[i], bo);
         }
-        if (NW > 1) __syncthreads();   // the ring slot of row rr - 3 dir is reused next
+        // the ring slot of row rr - 3 dir is reused next: with one wave the
+        // wave barrier keeps the compiler from moving the next row's LDS
+        // writes above this row's last reads (the hardware keeps LDS
+        // accesses of a wave in order)
+        if (NW > 1)
+            __syncthreads();
+        else
+            __builtin_amdgcn_wave_barrier();
     };
 
 #pragma unroll
@@ -1332,9 +1335,15 @@ __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __rest
     }
 }
 
-__global__ void k_batch_tick(int64_t* t_dev)
+__global__ void k_batch_tick(int64_t* t_dev, CaseRec* __restrict__ cases, int n_cases, const int* __restrict__ active)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) t_dev[0] += 1;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c == 0) t_dev[0] += 1;
+    if (c < n_cases && !active[c]) {
+        float* a = cases[c].buf[0];
+        cases[c].buf[0] = cases[c].buf[1];
+        cases[c].buf[1] = a;
+    }
 }
 
 __global__ void k_batch_set_time(int64_t* t_dev, int64_t t)
@@ -1554,9 +1563,10 @@ hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int p
     return hipGetLastError();
 }
 
-hipError_t launch_batch_tick(int64_t* t_dev, hipStream_t st)
+hipError_t launch_batch_tick(int64_t* t_dev, CaseRec* cases, int n_cases, const int* active, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_batch_tick, dim3(1), dim3(64), 0, st, t_dev);
+    hipLaunchKernelGGL(k_batch_tick, dim3((unsigned)std::max(1, (n_cases + 255) / 256)), dim3(256), 0, st, t_dev,
+                       cases, n_cases, active);
     return hipGetLastError();
 }
 

@@ -57,6 +57,7 @@ _lib = None
 EXPORTS = ["ij_params_default", "ij_create", "ij_destroy", "ij_last_error", "ij_required_bytes",
            "ij_attach_buffers", "ij_set_wall", "ij_init_distance", "ij_init_phi", "ij_init_default",
            "ij_step", "ij_step_reference", "ij_time", "ij_get_moments", "ij_get_state", "ij_set_state",
+           "ij_state_bytes", "ij_save_state", "ij_load_state",
            "ij_diag_sample", "ij_get_row_profile", "ij_get_samples", "ij_get_diagnostics", "ij_check",
            "ij_derived", "ij_set_tiling", "ij_autotune",
            "ij_batch_create", "ij_batch_destroy", "ij_batch_last_error", "ij_batch_size", "ij_batch_case",
@@ -65,7 +66,8 @@ EXPORTS = ["ij_params_default", "ij_create", "ij_destroy", "ij_last_error", "ij_
            "ij_mlp_create", "ij_mlp_destroy", "ij_mlp_last_error", "ij_mlp_param_count", "ij_mlp_set_weights",
            "ij_mlp_get_weights", "ij_mlp_set_scaling", "ij_mlp_gradients", "ij_mlp_train", "ij_mlp_predict",
            "ij3_create", "ij3_destroy", "ij3_last_error", "ij3_init", "ij3_step", "ij3_time", "ij3_get_moments",
-           "ij3_get_state", "ij3_set_state", "ij3_sample"]
+           "ij3_get_state", "ij3_set_state", "ij3_state_bytes", "ij3_save_state", "ij3_load_state",
+           "ij3_sample"]
 
 _INT3 = ["nx", "ny", "nz", "bc_y", "force_rows", "t_pos", "t_neg", "t_idle", "periodic_pulse"]
 _DBL3 = ["rho_ink", "rho_amb", "sigma", "width", "gamma", "tau_ink", "tau_amb", "tau_phi", "theta_inner",
@@ -112,6 +114,9 @@ def load(path: str = LIB_PATH):
         "ij_get_moments": (st, [vp, vp, vp, vp, vp, vp]),
         "ij_get_state": (st, [vp, vp, vp, vp]),
         "ij_set_state": (st, [vp, vp, vp, i64, vp]),
+        "ij_state_bytes": (st, [vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "ij_save_state": (st, [vp, vp, ctypes.c_size_t, vp]),
+        "ij_load_state": (st, [vp, vp, ctypes.c_size_t, vp]),
         "ij_diag_sample": (st, [vp, vp]),
         "ij_get_row_profile": (st, [vp, vp, vp, vp]),
         "ij_get_samples": (st, [vp, ctypes.POINTER(IJSample), i64, ctypes.POINTER(i64), vp]),
@@ -152,6 +157,9 @@ def load(path: str = LIB_PATH):
         "ij3_get_moments": (st, [vp, vp, vp, vp, vp, vp, vp]),
         "ij3_get_state": (st, [vp, vp, vp, vp]),
         "ij3_set_state": (st, [vp, vp, vp, i64, vp]),
+        "ij3_state_bytes": (st, [vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "ij3_save_state": (st, [vp, vp, ctypes.c_size_t, vp]),
+        "ij3_load_state": (st, [vp, vp, ctypes.c_size_t, vp]),
         "ij3_sample": (st, [vp, i64, vp, vp, vp, i64, i64, ctypes.POINTER(IJ3Drops), vp]),
     }
     for name, (res, args) in sig.items():
@@ -325,6 +333,18 @@ class Sim:
         ff, gg = self._dev(f, (9, self.ny, self.nx)), self._dev(g, (5, self.ny, self.nx))
         self._check(self.L.ij_set_state(self.h, _dptr(ff), _dptr(gg), int(t), _stream_ptr(stream)))
         self._keep_state = (ff, gg)
+
+    def save_state(self, stream=None) -> bytes:
+        """Checkpoint blob of the current state (:c:func:`ij_save_state`)."""
+        n = ctypes.c_size_t(0)
+        self._check(self.L.ij_state_bytes(self.h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self.L.ij_save_state(self.h, buf, n.value, _stream_ptr(stream)))
+        return buf.raw
+
+    def load_state(self, blob: bytes, stream=None):
+        """Resume from a blob of :meth:`save_state` (:c:func:`ij_load_state`)."""
+        self._check(self.L.ij_load_state(self.h, ctypes.c_char_p(blob), len(blob), _stream_ptr(stream)))
 
     def diag_sample(self, stream=None):
         self._check(self.L.ij_diag_sample(self.h, _stream_ptr(stream)))

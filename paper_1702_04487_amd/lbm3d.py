@@ -114,6 +114,18 @@ class Sim3D:
         self._check(self.L.ij3_set_state(self.h, _dptr(ft), _dptr(gt), int(t), _stream_ptr(stream)))
         self._keep_state = (ft, gt)
 
+    def save_state(self, stream=None) -> bytes:
+        """Checkpoint blob of the current state (:c:func:`ij3_save_state`)."""
+        n = ctypes.c_size_t(0)
+        self._check(self.L.ij3_state_bytes(self.h, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self.L.ij3_save_state(self.h, buf, n.value, _stream_ptr(stream)))
+        return buf.raw
+
+    def load_state(self, blob: bytes, stream=None):
+        """Resume from a blob of :meth:`save_state` (:c:func:`ij3_load_state`)."""
+        self._check(self.L.ij3_load_state(self.h, ctypes.c_char_p(blob), len(blob), _stream_ptr(stream)))
+
     def sample(self, row0: int = 0, a_min: Optional[int] = None, band: Optional[int] = None, stream=None) -> dict:
         """Sums, per-row ink profile and droplet segments of the current
         state; a drop needs a_min ink nodes (default 4 W^3), head and tail

@@ -103,11 +103,11 @@ def test_one_step_and_twenty_steps(oracle3d_mod, gpu_lib, name):
 def test_round_nozzle_pulse(oracle3d_mod, gpu_lib):
     """The 32 x 96 x 32 round nozzle through its +/- pulse (60 + 30 steps)
     and after: fields within 1e-5 relative L2 at every checkpoint to step
-    300.  At step 1000 n and phi still hold 1e-5; the velocity, which has
-    decayed tenfold to the spurious currents at the rim (max |u| ~ 1e-3), is
-    held to 1e-4: its error is the FP32 rounding of the populations
-    accumulated over 1000 steps (about 7e-8 absolute, sqrt(1000) times a
-    step's rounding), which a float remainder of g_0 does not change."""
+    300 and at step 1000, when the velocity has decayed tenfold to the
+    spurious currents at the rim (max |u| ~ 1e-3).  That late velocity is
+    the most sensitive quantity: it is held by the double-precision update
+    of g_0 and its stored remainder (with g_0 rounded to float every step
+    the relative error reached 7e-5)."""
     print("3-D round nozzle 1000 steps", flush=True)
     c = W.config_round_nozzle_small()
     o, g = _pair(oracle3d_mod, c["params"], c["wall"], c["distance"])
@@ -128,7 +128,7 @@ def test_round_nozzle_pulse(oracle3d_mod, gpu_lib):
     e = {k: rel_l2(mg[k][fl], mo[k][fl]) for k in ("n", "phi")}
     e["u"] = rel_l2(np.stack([mg[k][fl] for k in ("ux", "uy", "uz")]), np.stack([mo[k][fl] for k in ("ux", "uy", "uz")]))
     print("relative L2 at step 1000:", e)
-    assert e["n"] <= 1e-5 and e["phi"] <= 1e-5 and e["u"] <= 1e-4, e
+    assert e["n"] <= 1e-5 and e["phi"] <= 1e-5 and e["u"] <= 1e-5, e
 
 
 def test_diagnostics_match_oracle(oracle3d_mod, gpu_lib):
@@ -396,6 +396,31 @@ def test_checkpoint_resume(gpu_lib):
     fl = (c["wall"] == 0)[None]
     assert np.abs(np.where(fl, _np(fr) - _np(fa), 0)).max() < 1e-6
     assert np.abs(np.where(fl, _np(gr) - _np(ga), 0)).max() < 1e-6
+
+
+def test_checkpoint_resume_is_bitwise(gpu_lib):
+    """ij3_save_state at step 40 and ij3_load_state in a new handle: 41 more
+    steps end bit for bit where the uninterrupted run ends; a blob does not
+    load into a lattice with other walls."""
+    print("3-D checkpoint blob", flush=True)
+    import torch
+    from paper_1702_04487_amd import lbm3d
+    c = W.config_round_nozzle_small()
+    a = lbm3d.Sim3D(c["params"], c["wall"])
+    a.init_distance(c["distance"])
+    a.step(40)
+    blob = a.save_state()
+    b = lbm3d.Sim3D(c["params"], c["wall"])
+    b.load_state(blob)
+    assert b.t == 40
+    a.step(41)
+    b.step(41)
+    for x, y in zip(a.state(), b.state()):
+        assert bool((x.contiguous().view(torch.int32) == y.contiguous().view(torch.int32)).all())
+    other = c["wall"].copy()
+    other[0, 0, 0] = 2 if other[0, 0, 0] != 2 else 1
+    with pytest.raises(gpu_lib.LBMError):
+        lbm3d.Sim3D(c["params"], other).load_state(blob)
 
 
 def paper_fluid_nozzle3d():

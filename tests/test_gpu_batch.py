@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from parity_util import compare_fields, compare_state, np64, window_compare
 
 pytestmark = pytest.mark.gpu
 
@@ -111,7 +112,61 @@ def test_batch_graph_replay_equals_launches(gpu_lib):
     g.close()
 
 
+def test_batch_members_match_oracle(oracle_mod, gpu_lib):
+    """Each of the five uneven members of a batch against the FP64 oracle
+    run on its own: every distribution within 2e-6 after one step, and the
+    fields within 1e-5 relative L2 (n and phi also node by node against n0
+    and phi*) after 200 steps of their pulses."""
+    L, O = gpu_lib, oracle_mod
+    cases = _cases()
+    b = _batch(L, cases)
+    b.set_graph(20)
+    oracles = []
+    for p, wall, d in cases:
+        o = O.OracleSim(p, wall)
+        o.init_distance(d)
+        oracles.append(o)
+    b.step(1)
+    for i, (o, g) in enumerate(zip(oracles, b.cases)):
+        o.step(1)
+        print("batch member", i, "one step", compare_state(o, g, 2e-6), flush=True)
+    b.step(199)
+    for i, (o, g) in enumerate(zip(oracles, b.cases)):
+        o.step(199)
+        assert g.t == o.t == 200
+        print("batch member", i, "200 steps", compare_fields(o, g, 1e-5, elementwise=True), flush=True)
+    b.close()
+
+
+def test_sweep_table_cases_full_size_windows(oracle_mod, gpu_lib):
+    """Four cases of the 256-case sweep table (scaled variant, full lattice
+    sizes up to 384 x 3072) stepped as one batch: full-width windows of the
+    nozzle inlet, exit, chamber and top computed by the oracle agree with
+    the batch (distributions' moments within 2e-6, velocities within 1e-7)."""
+    L, O = gpu_lib, oracle_mod
+    table = W.sweep_cases(256, 1234, stable=True)[:4]
+    b = L.Batch([c["params"] for c in table], [W.case_wall(c) for c in table])
+    for sim, c in zip(b.cases, table):
+        sim.init_distance(W.case_distance(c))
+    k = 6
+    b.step(k)
+    for sim, c in zip(b.cases, table):
+        p = c["params"]
+        wall, d = W.case_wall(c), W.case_distance(c)
+        gm = {key: np64(v) for key, v in sim.moments().items()}
+        L_ = c["nozzle"][2]
+        for y0 in (0, L_ - 32, p["ny"] // 2, p["ny"] - 64):
+            errs = window_compare(O, p, wall, d, gm, y0, 0, 64, p["nx"], k, W.BC_OPEN)
+            assert errs["n"] < 2e-6 and errs["phi"] < 2e-6, (c["name"], y0, errs)
+            assert errs["ux"] < 1e-7 and errs["uy"] < 1e-7, (c["name"], y0, errs)
+    b.close()
+
+
 def test_batch_unstable_case_is_frozen_and_flagged(gpu_lib):
+    """A case driven far beyond the speed bound trips the guard: it is frozen
+    at the failing sample (its state stays that of the sample's step, read
+    back correctly after an odd number of further steps, and its later
+    samples all see that state) while the other cases go on bit for bit."""
     L = gpu_lib
     cases = _cases()
     p, wall, d = cases[1]
@@ -120,11 +175,19 @@ def test_batch_unstable_case_is_frozen_and_flagged(gpu_lib):
     b.set_graph(20)
     b.step(200)
     diag = b.cases[1].diagnostics()
-    assert diag["unstable_step"] >= 0 and b.cases[1].check() == L.IJ_ERR_UNSTABLE
+    tf = diag["unstable_step"]
+    assert tf >= 0 and b.cases[1].check() == L.IJ_ERR_UNSTABLE
     singles = _singles(L, [c for i, c in enumerate(cases) if i != 1], 200)
     for bc, sc in zip([c for i, c in enumerate(b.cases) if i != 1], singles):
         assert _same(bc, sc) and _same_samples(bc, sc)
         assert bc.check() == L.IJ_OK
+    # the frozen state: that of the case stepped alone to the failing sample
+    ref = _singles(L, [cases[1]], tf)[0]
+    for extra in (0, 7, 4):
+        b.step(extra)
+        assert _same(b.cases[1], ref), extra
+    smp = [x for x in b.cases[1].samples() if x["step"] >= tf]
+    assert len(smp) > 3 and all(x["mass_n"] == smp[0]["mass_n"] for x in smp)
     b.close()
 
 

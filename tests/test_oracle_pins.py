@@ -323,6 +323,37 @@ def test_shear_wave_viscosity(oracle_mod):
     assert rate == pytest.approx(nu * 2 * (1 - math.cos(k)), rel=5e-3)
 
 
+@pytest.mark.parametrize("phase", [-1.0, 0.0, 0.5])
+def test_shear_wave_viscosity_per_phase(oracle_mod, phase):
+    """The per-phase relaxation time (reading R4: C = clamp((phi/phi* + 1)/2,
+    0, 1), tau = tau_amb + C (tau_ink - tau_amb)) seen through the physical
+    viscosity: a shear wave in a uniform phase phi = phase * phi* decays at
+    nu k^2 with nu = (tau(phi) - 1/2)/3.  The ambient end (C = 0), the mid
+    point (C = 1/2, the mean of the two times) and an interior point
+    (C = 3/4) are each pinned by a decay rate: a wrong composition variable
+    or interpolation changes one of them."""
+    O = oracle_mod
+    nx, ny = 3, 64
+    tau_ink, tau_amb = 0.8, 1.1
+    p = W.base_params(nx, ny, bc_y=0, tau_ink=tau_ink, tau_amb=tau_amb)
+    s = _sim(O, p)
+    k = 2 * np.pi / ny
+    y = np.arange(ny)[:, None]
+    s.init_phi(np.full((ny, nx), phase * s.derived()["phi_star"]),
+               np.broadcast_to(1e-3 * np.sin(k * y), (ny, nx)).copy(), None)
+    amp = lambda: 2 * np.abs(np.fft.rfft(s.moments()["ux"][:, 1])[1]) / ny
+    s.step(200)
+    a0 = amp()
+    s.step(2000)
+    rate = math.log(a0 / amp()) / 2000
+    C = {-1.0: 0.0, 0.0: 0.5, 0.5: 0.75}[phase]
+    nu = (tau_amb + C * (tau_ink - tau_amb) - 0.5) / 3
+    assert rate == pytest.approx(nu * 2 * (1 - math.cos(k)), rel=5e-3)
+    # the phase itself is steady (uniform, no gradient to drive it)
+    ph = s.moments()["phi"]
+    assert np.abs(ph - phase * s.derived()["phi_star"]).max() < 1e-12
+
+
 def test_poiseuille_profile(oracle_mod):
     """Body-force driven channel between bounce-back walls (wall halfway
     between nodes): u(x) = F (x+1/2)(w-1/2-x) / (2 n0 nu)."""
