@@ -371,9 +371,26 @@ ij_status ij_mlp_train(ij_mlp *m, const float *x_dev, const float *y_dev, int32_
  * (standard deviation over the members) of each output (device [n][4]:
  * breakup step, drop velocity, drop volume in target units, and the
  * satellite probability); members (device [n_members][n][4]) optional.
+ * Without members the per-member outputs go to a buffer of the handle,
+ * allocated (hipMalloc) on the first call that needs it larger.
  * Asynchronous. */
 ij_status ij_mlp_predict(ij_mlp *m, const float *x_dev, int64_t n, float *mean_dev, float *spread_dev,
                          float *members_dev, void *stream);
+
+/* ij_mlp_predict (mean and spread) for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  Same kernels and results, bit for bit; the per-member
+ * outputs go to a fixed 8 MiB array the library holds on every device it
+ * runs on (until the process ends), whose address is looked up once per
+ * device on the first call.  The call allocates and frees nothing.
+ * Limits: n * n_members <= 524288 (131072 queries for 4 members), else
+ * IJ_ERR_INVALID_ARG; mean_dev and spread_dev are required; the current
+ * device must be the one the handle was created on (IJ_ERR_STATE).  Every
+ * call on a device shares that device's array: calls that overlap on one
+ * device (other streams, threads or handles) race and must be ordered by
+ * the caller.  Asynchronous. */
+ij_status ij_mlp_predict_noalloc(ij_mlp *m, const float *x_dev, int64_t n, float *mean_dev, float *spread_dev,
+                                 void *stream);
 
 /* ------------------------------------------------------------------------
  * Three-dimensional lattice (round nozzles).

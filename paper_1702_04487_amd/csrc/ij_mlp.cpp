@@ -20,6 +20,7 @@ thread_local std::string g_mlp_create_error;
 struct ij_mlp {
     MlpDev D{};
     MlpNorm N{};
+    int device = 0;           // the device that holds the parameters
     int64_t adam_steps = 0;   // Adam steps taken since the parameters were set
     float* members = nullptr; // prediction scratch [n_members][cap][4]
     int64_t members_cap = 0;
@@ -89,6 +90,10 @@ ij_status ij_mlp_create(int32_t n_members, ij_mlp** out)
     if (n_members < 1 || n_members > 64) return mfail(nullptr, IJ_ERR_INVALID_ARG, "n_members must lie in [1, 64]");
     ij_mlp* m = new ij_mlp();
     m->D.n_members = n_members;
+    if (hipGetDevice(&m->device) != hipSuccess) {
+        delete m;
+        return mfail(nullptr, IJ_ERR_DEVICE, "hipGetDevice failed");
+    }
     m->D.scratch_per_member = mlp_scratch_bytes();
     const size_t np = (size_t)n_members * kMlpParams * sizeof(float);
     if (hipMalloc(&m->D.w, np) != hipSuccess || hipMalloc(&m->D.m, np) != hipSuccess ||
@@ -240,6 +245,27 @@ ij_status ij_mlp_predict(ij_mlp* m, const float* x_dev, int64_t n, float* mean_d
         mem = m->members;
     }
     const hipError_t e = mlp_launch_infer(m->D, m->N, x_dev, (int)n, mem, mean_dev, spread_dev, (hipStream_t)stream);
+    return e == hipSuccess ? IJ_OK : mhip(m, e, "inference kernels");
+}
+
+ij_status ij_mlp_predict_noalloc(ij_mlp* m, const float* x_dev, int64_t n, float* mean_dev, float* spread_dev,
+                                 void* stream)
+{
+    if (!m) return IJ_ERR_INVALID_ARG;
+    if (n == 0) return IJ_OK;
+    if (!x_dev || !mean_dev || !spread_dev) return mfail(m, IJ_ERR_INVALID_ARG, "x, mean and spread are required");
+    const int64_t max_n = (int64_t)(kMlpStaticScratchFloats / ((size_t)m->D.n_members * kMlpOut));
+    if (n < 0 || n > max_n)
+        return mfail(m, IJ_ERR_INVALID_ARG,
+                     "n must lie in [0, " + std::to_string(max_n) + "]: the fixed scratch holds " +
+                         std::to_string(kMlpStaticScratchFloats / kMlpOut) + " query-member outputs");
+    int dev = -1;
+    IJM_HIP(m, hipGetDevice(&dev));
+    if (dev != m->device) return mfail(m, IJ_ERR_STATE, "the current device is not the handle's device");
+    float* scratch_dev = nullptr;
+    IJM_HIP(m, mlp_static_scratch(&scratch_dev));
+    const hipError_t e =
+        mlp_launch_infer(m->D, m->N, x_dev, (int)n, scratch_dev, mean_dev, spread_dev, (hipStream_t)stream);
     return e == hipSuccess ? IJ_OK : mhip(m, e, "inference kernels");
 }
 

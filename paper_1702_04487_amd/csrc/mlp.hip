@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "mlp_core.h"
 
 namespace ij {
@@ -446,6 +448,32 @@ hipError_t mlp_launch_refresh(const MlpDev& D, hipStream_t st)
 {
     hipLaunchKernelGGL(k_mlp_refresh, dim3(D.n_members), dim3(MT), 0, st, D);
     return hipGetLastError();
+}
+
+// Per-member outputs of ij_mlp_predict_noalloc: a file-scope device array,
+// one copy per GPU, alive until the process ends.  In host code `scratch`
+// names a host-side stand-in, never the device memory: host code uses only
+// the address mlp_static_scratch looks up.
+static __device__ __align__(256) float scratch[kMlpStaticScratchFloats];
+
+hipError_t mlp_static_scratch(float** ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static float* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<float*>(p);
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t mlp_launch_infer(const MlpDev& D, const MlpNorm& N, const float* X, int n, float* members, float* mean,

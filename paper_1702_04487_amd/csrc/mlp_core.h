@@ -101,4 +101,13 @@ hipError_t mlp_launch_refresh(const MlpDev& D, hipStream_t st);
 hipError_t mlp_launch_infer(const MlpDev& D, const MlpNorm& N, const float* X, int n, float* members, float* mean,
                             float* spread, hipStream_t st);
 
+// Floats of the fixed per-device scratch array of the prediction that
+// allocates nothing (8 MiB: the per-member outputs of n * n_members <=
+// 524288 query-member pairs).
+constexpr size_t kMlpStaticScratchFloats = (size_t)1 << 21;
+// Device address of that array on the current device: looked up with
+// hipGetSymbolAddress on the first call for each device (with that device
+// current) and kept for the life of the process.  No allocation.
+hipError_t mlp_static_scratch(float** ptr);
+
 }  // namespace ij

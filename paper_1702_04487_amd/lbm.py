@@ -65,6 +65,7 @@ EXPORTS = ["ij_params_default", "ij_create", "ij_destroy", "ij_last_error", "ij_
            "ij_batch_autotune",
            "ij_mlp_create", "ij_mlp_destroy", "ij_mlp_last_error", "ij_mlp_param_count", "ij_mlp_set_weights",
            "ij_mlp_get_weights", "ij_mlp_set_scaling", "ij_mlp_gradients", "ij_mlp_train", "ij_mlp_predict",
+           "ij_mlp_predict_noalloc",
            "ij3_create", "ij3_destroy", "ij3_last_error", "ij3_init", "ij3_step", "ij3_time", "ij3_get_moments",
            "ij3_get_state", "ij3_set_state", "ij3_state_bytes", "ij3_save_state", "ij3_load_state",
            "ij3_sample"]
@@ -148,6 +149,7 @@ def load(path: str = LIB_PATH):
         "ij_mlp_gradients": (st, [vp, vp, vp, i32, vp, vp, vp]),
         "ij_mlp_train": (st, [vp, vp, vp, i32, vp, i32, i32, ctypes.c_float, vp, vp]),
         "ij_mlp_predict": (st, [vp, vp, i64, vp, vp, vp, vp]),
+        "ij_mlp_predict_noalloc": (st, [vp, vp, i64, vp, vp, vp]),
         "ij3_create": (st, [ctypes.POINTER(IJ3Params), vp, ctypes.POINTER(vp)]),
         "ij3_destroy": (None, [vp]),
         "ij3_last_error": (ctypes.c_char_p, [vp]),
@@ -556,3 +558,15 @@ class MLP:
                                           _dptr(mem) if mem is not None else None, _stream_ptr(stream)))
         self._keep_pred = xt
         return (mean, spread, mem) if members else (mean, spread)
+
+    def predict_into(self, x, mean, spread, stream=None):
+        """Prediction into caller tensors (mean, spread: [n, 4] float32 on the
+        device) through :c:func:`ij_mlp_predict_noalloc`, which allocates
+        nothing; x must already be a contiguous float32 [n, 7] device tensor."""
+        import torch
+        n = int(x.shape[0])
+        for t in (x, mean, spread):
+            assert isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous() and t.dtype == torch.float32
+        assert tuple(x.shape) == (n, 7) and tuple(mean.shape) == (n, 4) and tuple(spread.shape) == (n, 4)
+        self._check(self.L.ij_mlp_predict_noalloc(self.h, _dptr(x), n, _dptr(mean), _dptr(spread),
+                                                  _stream_ptr(stream)))
