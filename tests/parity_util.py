@@ -84,3 +84,30 @@ def window_compare(O, p_full, wall, d, g_mom, y0, x0, hw, ww, k, bc_y):
         ov = mo[key][inner][fl]
         out[key] = np.abs(gv - ov).max()
     return out
+
+
+def oracle_series(O, p, wall, row0, K, n_steps, init=None, stop=None):
+    """Diagnostics samples of the FP64 oracle every K steps from step 0 to
+    n_steps (or until stop(series) is true): the per-sample segment records
+    of the rows y >= row0.  init(o) sets the initial state (default: ink in
+    the rows below row0 with a flat meniscus)."""
+    o = O.OracleSim(p, wall)
+    if init is None:
+        import workloads as W
+        o.init_distance(W.meniscus_distance(p["nx"], p["ny"], row0))
+    else:
+        init(o)
+    series = []
+    for k in range(0, n_steps + 1, K):
+        if o.t < k:
+            o.step(k - o.t)
+        d = o.diag(row0)
+        seg = O.segments(d["row_count"], d["row_uy"], row0, 4 * p["width"] ** 2, O.band_rows(p["width"]))
+        seg["step"] = k
+        seg["nan_count"] = d["nan_count"]
+        series.append(seg)
+        if stop is not None and stop(series):
+            break
+    o.close()
+    return series
+

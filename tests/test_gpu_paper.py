@@ -21,23 +21,32 @@ def test_paper_preset_matches_oracle(oracle_mod, gpu_lib):
     for t in (100, 300, 600):
         o.step(t - o.t)
         g.step(t - g.t)
-        for k, v in _compare_fields(o, g, 1e-5).items():
+        for k, v in _compare_fields(o, g, 1e-5, elementwise=True).items():
             worst[k] = max(worst.get(k, 0.0), v)
     print("worst relative L2:", worst)
 
 
 THETAS = (30.0, 60.0, 90.0, 120.0, 150.0)
 SIGMAS = (20.0, 40.0, 60.0, 85.0)   # mN/m
+# A weaker push and pull (found by a scan of the unprinted amplitudes) that
+# puts the 90-degree breakup inside the paper's 50-60 us window
+WINDOW_PULSE = dict(f_pos=0.04, f_neg=0.0464)
 
 
 def test_paper_trends(gpu_lib):
     """Discussion, Figs. 5 and 7: with the paper preset (pulse of this
     preset, see config_paper), the filament breaks up later on a more
     hydrophobic nozzle wall and sooner with a higher surface tension.  The
-    absolute times are not pinned (the paper prints no force amplitudes);
-    the signs of the trends are, and the recoil of the tail after the
-    pinch-off (Fig. 3)."""
-    specs = [dict(theta=t) for t in THETAS] + [dict(sigma_mn_per_m=s) for s in SIGMAS]
+    force amplitudes are not printed, so the absolute times are pinned at
+    one point only: with the weaker WINDOW_PULSE the 90-degree filament
+    breaks up between 50 and 60 us, as in the paper's validation run
+    (Results, "Reproducing the experiment"; Fig. 4(c): 51.89 us), and the
+    contact-angle trend holds there too.  (That pulse is too weak to pinch
+    the filament off above 30 mN/m, so the surface-tension sweep keeps the
+    preset's pulse.)  Also the recoil of the tail after the pinch-off
+    (Fig. 3)."""
+    specs = [dict(theta=t) for t in THETAS] + [dict(sigma_mn_per_m=s) for s in SIGMAS] + \
+        [dict(theta=t, **WINDOW_PULSE) for t in THETAS]
     cfgs = [W.config_paper(**sp) for sp in specs]
     b = gpu_lib.Batch([dict(c["params"], diag_row0=c["row0"], diag_every=50) for c in cfgs],
                       [c["wall"] for c in cfgs])
@@ -66,7 +75,11 @@ def test_paper_trends(gpu_lib):
           f"drop length {length[0]} -> {length[-1]} rows over {u.microseconds(after[-1]['step'] - tb):.1f} us")
     assert recoil > 0 and length[-1] < length[0] - 5
     tb_theta = [r[0] for r in res[:len(THETAS)]]
-    tb_sigma = [r[0] for r in res[len(THETAS):]]
+    tb_sigma = [r[0] for r in res[len(THETAS):len(THETAS) + len(SIGMAS)]]
+    tb_window = [r[0] for r in res[len(THETAS) + len(SIGMAS):]]
+    # the paper's validation window at 90 degrees, and the contact-angle trend at that pulse
+    assert 50.0 <= tb_window[THETAS.index(90.0)] <= 60.0, tb_window
+    assert all(a <= b for a, b in zip(tb_window, tb_window[1:])) and tb_window[-1] > tb_window[0] + 2.0
     # breakup later with the contact angle (paper: 37 -> 62 us from 30 to 150 deg)
     assert all(a <= b for a, b in zip(tb_theta, tb_theta[1:])) and tb_theta[-1] > tb_theta[0] + 2.0
     # breakup sooner with the surface tension (paper: 18 us sooner from 20 to 85 mN/m)
