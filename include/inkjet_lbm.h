@@ -127,9 +127,10 @@ void ij_destroy(ij_sim *s);
  * s is NULL).  Valid until the next call on the handle. */
 const char *ij_last_error(const ij_sim *s);
 
-/* Bytes of ONE distribution buffer for the given parameters: 14 float
- * planes of ny rows with a 64-float aligned row pitch (9 f, 5 g) and one
- * 16-bit plane (low-order part of g_0). */
+/* Bytes of ONE distribution buffer for the given parameters: for each
+ * lattice row, 14 rows of floats with a 64-float aligned pitch (9 f, 5 g:
+ * the populations of one lattice row are stored together), then one 16-bit
+ * plane [ny][pitch] (low-order part of g_0). */
 ij_status ij_required_bytes(const ij_params *p, size_t *bytes);
 
 /* Use caller-owned device buffers (each >= ij_required_bytes, 256-byte
@@ -188,7 +189,7 @@ ij_status ij_set_state(ij_sim *s, const float *f_dev, const float *g_dev, int64_
 
 /* Checkpoint and bit-exact resume of the state the update works on (Eqs. 3
  * and 8 advance f and g alone; the pulse phase of Fig. 1 follows from the
- * step counter).  The blob is a 64-byte header (magic "IJSTATE1", lattice
+ * step counter).  The blob is a 64-byte header (magic "IJSTATE2", lattice
  * size, row pitch, step counter, a hash of the wall mask, payload size)
  * followed by the current distribution buffer exactly as the kernels store
  * it: the shifted f planes, the g planes and the 16-bit remainder plane of
@@ -231,16 +232,18 @@ ij_status ij_check(ij_sim *s, void *stream);
 ij_status ij_derived(const ij_sim *s, double out[8]);
 
 /* Autotuner: time trial_steps (2..10000) fused steps for each candidate
- * tile shape (1, 2, 4 waves x 8, 16, 32, 64 rows), keep the fastest, and
+ * tile shape (1, 2, 4 waves x 1, 8, 16, 32, 64 rows), keep the fastest, and
  * restore the distributions (the step counter does not move).  Outputs may
  * be NULL.  Synchronises the stream. */
 ij_status ij_autotune(ij_sim *s, int32_t trial_steps, void *stream, int32_t *waves_x, int32_t *rows_per_block,
                       double *ms_per_step);
 
-/* Tile shape of the fused collide-stream kernel: waves across x per
- * workgroup (1, 2 or 4) and rows per workgroup (1..1024); the default is
- * 4 waves (256 columns) by 32 rows.  0 keeps the current value.  Results
- * do not depend on the tile shape (bit for bit). */
+/* Tile shape of the fused collide-stream kernels: waves across x per
+ * workgroup (1, 2 or 4) and rows per workgroup (1..1024).  With 1 row the
+ * rows away from walls and open rows are updated without a walk (one wave
+ * per 64 columns of a row); with more, each workgroup walks its block of
+ * rows.  The default is 4 waves (256 columns) by 1 row.  0 keeps the
+ * current value.  Results do not depend on the tile shape (bit for bit). */
 ij_status ij_set_tiling(ij_sim *s, int32_t waves_x, int32_t rows_per_block);
 
 /* ------------------------------------------------------------------ batches

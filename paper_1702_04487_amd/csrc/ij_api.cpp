@@ -131,6 +131,7 @@ void fill_kparams(ij_sim* s)
     K.force_rows = (int)std::min<int64_t>(p.force_rows, s->ny);
     K.diag_row0 = (int)p.diag_row0;
     K.plane = (unsigned)s->plane;
+    K.rs = (unsigned)(ij::kFloatPlanes * s->pitch);
     K.phi_star = s->phi_star;
     K.beta4 = 4.0 * s->beta;
     K.kappa = s->kappa;
@@ -682,7 +683,7 @@ ij_status ij_save_state(ij_sim* s, void* blob, size_t bytes, void* stream)
         if (r != IJ_OK) return r;
     }
     StateHeader h{};
-    std::memcpy(h.magic, "IJSTATE1", 8);
+    std::memcpy(h.magic, "IJSTATE2", 8);
     h.nx = s->nx;
     h.ny = s->ny;
     h.nz = 1;
@@ -703,7 +704,7 @@ ij_status ij_load_state(ij_sim* s, const void* blob, size_t bytes, void* stream)
     StateHeader h;
     std::memcpy(&h, blob, sizeof h);
     const size_t payload = buffer_bytes(s->plane);
-    if (std::memcmp(h.magic, "IJSTATE1", 8) != 0) return fail(s, IJ_ERR_INVALID_ARG, "not a checkpoint of this library");
+    if (std::memcmp(h.magic, "IJSTATE2", 8) != 0) return fail(s, IJ_ERR_INVALID_ARG, "not a checkpoint of this library");
     if (h.nx != s->nx || h.ny != s->ny || h.nz != 1 || h.pitch != s->pitch || h.payload != payload)
         return fail(s, IJ_ERR_INVALID_ARG, "checkpoint of a different lattice size");
     if (h.wall_hash != fnv1a(s->wall_host.data(), s->wall_host.size()))
@@ -835,7 +836,9 @@ ij_status ij_autotune(ij_sim* s, int32_t trial_steps, void* stream, int32_t* wav
     if (!s->initialised) return fail(s, IJ_ERR_STATE, "autotune before init");
     if (trial_steps < 2 || trial_steps > 10000) return fail(s, IJ_ERR_INVALID_ARG, "trial_steps must lie in [2, 10000]");
     hipStream_t st = (hipStream_t)stream;
-    static const int cand[][2] = {{1, 8}, {1, 16}, {1, 32}, {2, 8}, {2, 16}, {2, 32}, {4, 8}, {4, 16}, {4, 32}, {4, 64}};
+    // rows_per_block 1: the row kernel (no walk) for plain rows
+    static const int cand[][2] = {{1, 1},  {2, 1},  {4, 1},  {1, 8},  {1, 16}, {1, 32}, {2, 8},
+                                  {2, 16}, {2, 32}, {4, 8},  {4, 16}, {4, 32}, {4, 64}};
     // trial steps run on the live buffers from a snapshot that is restored
     const size_t bytes = buffer_bytes(s->plane);
     void* saved = nullptr;

@@ -53,7 +53,7 @@ struct ij_sim {
     int64_t t = 0;
     bool initialised = false;
     int64_t unstable_step = -1;
-    int waves_x = 4, rows_per_block = 32;
+    int waves_x = 4, rows_per_block = 1;   // 1: plain rows by the row kernel
     // rows of each strip the plain collide-stream path may take, and the
     // tiles that hold the other rows (rebuilt with the wall or the tiling)
     uint8_t* plain = nullptr;

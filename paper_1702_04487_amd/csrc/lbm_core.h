@@ -6,9 +6,11 @@
 
 namespace ij {
 
-// Buffer layout: 14 float planes (f_0..f_8 shifted by w_i n0, then g_0..g_4)
-// followed by one plane of 16-bit words holding the bfloat16 remainder
-// g_0 - float(g_0) of the rest order-parameter population.
+// Buffer layout: per lattice row, 14 consecutive rows of pitch floats
+// (f_0..f_8 shifted by w_i n0, then g_0..g_4), so population i of node
+// (x, y) is at (14 y + i) pitch + x; after the ny such row groups, one plane
+// [ny][pitch] of 16-bit words holding the bfloat16 remainder g_0 - float(g_0)
+// of the rest order-parameter population.
 constexpr int kFloatPlanes = 14;
 constexpr int kMaxRowsPerBlock = 1024;   // rows of one tile (LDS row flags)
 
@@ -20,7 +22,9 @@ struct KParams {
     int bc_open;          // 1: "fully developed" top and bottom rows
     int force_rows;       // body force on fluid nodes with y < force_rows
     int diag_row0;        // rows y >= diag_row0 count ink in a diagnostics sample
-    unsigned plane;       // elements per plane (ny * pitch)
+    unsigned plane;       // nodes of a padded lattice (ny * pitch): the size of the
+                          // g_0 remainder plane, the wall mask and the phi field
+    unsigned rs;          // floats per lattice row of a buffer (14 * pitch)
     // double-precision order-parameter constants
     double phi_star, beta4, kappa, gamma, omega_phi, inv_width;
     double wet[4];        // ghost offset 2 Omega phi*/W per wall class (index 1, 2)

@@ -2,14 +2,18 @@
 // (arXiv:1702.04487, Methods Eqs. 3-10; actuation of Fig. 1; wetting walls and
 // "fully developed" rows of Results, "Reproducing the experiment").
 //
-// Storage: one buffer = 14 float planes of ny rows x pitch columns (pitch a
-// multiple of 64) plus one 16-bit plane:
-//   planes 0..8   f_i - w_i n0 (D2Q9 distributions shifted by their rest
+// Storage: one buffer = 14 float populations per node, then one 16-bit plane.
+// The populations of one lattice row are 14 consecutive rows of pitch floats
+// (pitch = nx rounded up to 64): population i of node (x, y) sits at
+// (14 y + i) pitch + x, so a row's populations are one contiguous region
+// (one stream of memory per lattice row, not 14 streams planes apart):
+//   i = 0..8      f_i - w_i n0 (D2Q9 distributions shifted by their rest
 //                 value, which keeps the low-order bits of the small velocity
 //                 signal in FP32);
-//   planes 9..13  g_0..g_4 (D2Q5);
-//   16-bit plane  bfloat16 of g_0 - float(g_0): g_0 carries +-phi* and is the
-//                 only population whose FP32 rounding would quantise phi.
+//   i = 9..13     g_0..g_4 (D2Q5);
+//   16-bit plane  [ny][pitch] bfloat16 of g_0 - float(g_0): g_0 carries
+//                 +-phi* and is the only population whose FP32 rounding would
+//                 quantise phi.
 // Two buffers A (current, pre-collision) and B (next) alternate.
 //
 // Velocities c_0=(0,0) c_1=(1,0) c_2=(0,1) c_3=(-1,0) c_4=(0,-1)
@@ -222,6 +226,12 @@ __device__ __forceinline__ uint8_t mask_at(const KParams& P, const uint8_t* wall
     return wall[(unsigned)y * P.pitch + x];
 }
 
+// index of population i of node (x, y) in a buffer
+__device__ __forceinline__ size_t pidx(const KParams& P, int i, int x, int y)
+{
+    return (size_t)(unsigned)y * P.rs + (unsigned)(i * P.pitch + x);
+}
+
 __device__ __forceinline__ const uint16_t* lo_plane(const float* A, const KParams& P)
 {
     return reinterpret_cast<const uint16_t*>(A + (size_t)kFloatPlanes * P.plane);
@@ -246,7 +256,6 @@ struct StreamCtx {
     const KParams* P;
     float* B;
     int x, y;
-    unsigned own;  // y * pitch + x
 };
 
 // Stream one post-collision population of node (x, y): to x + c_I, or back
@@ -275,16 +284,15 @@ __device__ __forceinline__ void stream_one(const StreamCtx& c, float hv, float g
     const bool fl = dest_mask() == 0;
     const int d = fl ? I : OPP;
     const int wx = fl ? tx : c.x, wy = fl ? ty : c.y;
-    const unsigned woff = fl ? ((unsigned)ty * P.pitch + tx) : c.own;
     const float v = IS_G ? hv + P.omq * (fl ? g_dest : g_self) : hv;
     const int pl = IS_G ? 9 + d : d;
-    c.B[(size_t)pl * P.plane + woff] = v;
+    c.B[pidx(P, pl, wx, wy)] = v;
     if (P.bc_open) {
         const int cyd = fl ? DY : -DY;
         if (cyd > 0 && wy == 1 && open_fluid(0, fl ? DX : 0))
-            c.B[(size_t)pl * P.plane + wx] = v;
+            c.B[pidx(P, pl, wx, 0)] = v;
         if (cyd < 0 && wy == P.ny - 2 && open_fluid(1, fl ? DX : 0))
-            c.B[(size_t)pl * P.plane + (unsigned)(P.ny - 1) * P.pitch + wx] = v;
+            c.B[pidx(P, pl, wx, P.ny - 1)] = v;
     }
 }
 
@@ -320,11 +328,10 @@ __device__ __forceinline__ void stream_shifted(const ShiftCtx& c, float v, float
     }
     const int pl = IS_G ? 9 + I : I;
     auto put = [&](int plane_idx, int cyd, int wx, int wy, int dxo, float val) {
-        c.B[(size_t)plane_idx * P.plane + (unsigned)wy * P.pitch + wx] = val;
+        c.B[pidx(P, plane_idx, wx, wy)] = val;
         if (P.bc_open) {
-            if (cyd > 0 && wy == 1 && open_fluid(0, dxo)) c.B[(size_t)plane_idx * P.plane + wx] = val;
-            if (cyd < 0 && wy == P.ny - 2 && open_fluid(1, dxo))
-                c.B[(size_t)plane_idx * P.plane + (unsigned)(P.ny - 1) * P.pitch + wx] = val;
+            if (cyd > 0 && wy == 1 && open_fluid(0, dxo)) c.B[pidx(P, plane_idx, wx, 0)] = val;
+            if (cyd < 0 && wy == P.ny - 2 && open_fluid(1, dxo)) c.B[pidx(P, plane_idx, wx, P.ny - 1)] = val;
         }
     };
     // receive: this lane's column at row y + DY, pushed from column x - DX
@@ -352,9 +359,8 @@ __device__ __forceinline__ void phi_node(const KParams& P, const float* __restri
 {
     const unsigned k = (unsigned)y * P.pitch + x;
     if (wall[k]) return;
-    const float* g = A + (size_t)9 * P.plane;
-    phi[k] = phi_of(g[k], g[(size_t)P.plane + k], g[2 * (size_t)P.plane + k], g[3 * (size_t)P.plane + k],
-                    g[4 * (size_t)P.plane + k], bf16_to_float(lo_plane(A, P)[k]));
+    phi[k] = phi_of(A[pidx(P, 9, x, y)], A[pidx(P, 10, x, y)], A[pidx(P, 11, x, y)], A[pidx(P, 12, x, y)],
+                    A[pidx(P, 13, x, y)], bf16_to_float(lo_plane(A, P)[k]));
 }
 
 __global__ void k_phi_from_g(KParams P, const float* __restrict__ A, const uint8_t* __restrict__ wall,
@@ -425,9 +431,9 @@ __global__ void k_collide_ref(KParams P, const float* __restrict__ A, float* __r
     float f[9], g[5], fs[9], h[5];
     double st[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = A[(size_t)i * P.plane + k];
+    for (int i = 0; i < 9; ++i) f[i] = A[pidx(P, i, x, y)];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) g[i] = A[(size_t)(9 + i) * P.plane + k];
+    for (int i = 0; i < 5; ++i) g[i] = A[pidx(P, 9 + i, x, y)];
     const float lo = bf16_to_float(lo_plane(A, P)[k]);
     load_stencil(P, phi, x, y, st);
     Macro m;
@@ -435,10 +441,10 @@ __global__ void k_collide_ref(KParams P, const float* __restrict__ A, float* __r
     uint16_t g0l;
     node_collide(P, f, g, lo, st, y < P.force_rows ? P.fb : 0.f, fs, h, g0h, g0l, m);
 
-    B[k] = fs[0];
-    B[(size_t)9 * P.plane + k] = g0h;
+    B[pidx(P, 0, x, y)] = fs[0];
+    B[pidx(P, 9, x, y)] = g0h;
     lo_plane(B, P)[k] = g0l;
-    const StreamCtx c{&P, B, x, y, k};
+    const StreamCtx c{&P, B, x, y};
     auto open_fluid = [&](int top, int dx) {
         const int cx = wrapx(x + dx, P.nx);
         return wall[top ? (unsigned)(P.ny - 1) * P.pitch + cx : (unsigned)cx] == 0;
@@ -448,7 +454,7 @@ __global__ void k_collide_ref(KParams P, const float* __restrict__ A, float* __r
         if (P.bc_open && (y + dy < 0 || y + dy >= P.ny)) return 0.f;
         int ty = y + dy;
         ty = ty < 0 ? ty + P.ny : (ty >= P.ny ? ty - P.ny : ty);
-        return A[(size_t)(9 + i) * P.plane + (unsigned)ty * P.pitch + wrapx(x + dx, P.nx)];
+        return A[pidx(P, 9 + i, wrapx(x + dx, P.nx), ty)];
     };
 #define IJ_MASK(DX, DY) [&]() { return mask_at(P, wall, x + (DX), y + (DY)); }
     stream_one<1, false>(c, fs[1], 0.f, 0.f, IJ_MASK(1, 0), open_fluid);
@@ -609,19 +615,13 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
     for (int i = t; i < y1 - y0; i += BW)
         s_mine[i] = (plain_rows[(size_t)strip * P.ny + y0 + i] != 0) == PLAIN;
 
-    // plane bases (uniform) and 32-bit byte offsets
-    const size_t pl = P.plane;
-    const float* Af[9];
-    float* Bf[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) { Af[i] = A + i * pl; Bf[i] = B + i * pl; }
-    const float* Ag[5];
-    float* Bg[5];
-#pragma unroll
-    for (int i = 0; i < 5; ++i) { Ag[i] = A + (9 + i) * pl; Bg[i] = B + (9 + i) * pl; }
+    // row bases (uniform over the workgroup: 64-bit) and 32-bit byte offsets
+    // of population i of column xx within a row
     const uint16_t* Alo = lo_plane(A, P);
     uint16_t* Blo = lo_plane(B, P);
-    auto boff = [&](int xx, int yy) -> unsigned { return ((unsigned)yy * (unsigned)P.pitch + (unsigned)xx) << 2; };
+    auto arow = [&](int yy) { return A + (size_t)(unsigned)yy * P.rs; };
+    auto brow = [&](int yy) { return B + (size_t)(unsigned)yy * P.rs; };
+    auto boff = [&](int i, int xx) -> unsigned { return ((unsigned)i * (unsigned)P.pitch + (unsigned)xx) << 2; };
     auto ldf = [](const float* base, unsigned bo) { return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + bo); };
     auto stf = [](float* base, unsigned bo, float v) { *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + bo) = v; };
 
@@ -651,12 +651,13 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
         }
         const unsigned k = (unsigned)ry * P.pitch + xc;
         const unsigned kh = (unsigned)ry * P.pitch + hx;
+        const float* Ar = arow(ry);
         m = wall[k];
         mh = wall[kh];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) g[i] = ldf(Ag[i], k << 2);
+        for (int i = 0; i < 5; ++i) g[i] = ldf(Ar, boff(9 + i, xc));
 #pragma unroll
-        for (int i = 0; i < 5; ++i) gh[i] = ldf(Ag[i], kh << 2);
+        for (int i = 0; i < 5; ++i) gh[i] = ldf(Ar, boff(9 + i, hx));
         lo = Alo[k];
         loh = Alo[kh];
     };
@@ -769,9 +770,9 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
                 node_collide(P, rf[S], gcur, bf16_to_float(s_lo[sc][t]), st, rc < P.force_rows ? fb : 0.f, fs,
                              h, g0h, g0l, mac);
                 if constexpr (SAMPLE) sample_node(mac, rc >= P.diag_row0, dterm);
-                const unsigned bo = boff(x, rc);
-                stf(Bf[0], bo, fs[0]);
-                stf(Bg[0], bo, g0h);
+                float* Bc = brow(rc);
+                stf(Bc, boff(0, x), fs[0]);
+                stf(Bc, boff(9, x), g0h);
                 Blo[(unsigned)rc * P.pitch + x] = g0l;
                 if constexpr (!PLAIN) {
 #pragma unroll
@@ -790,37 +791,39 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
                 if (active) {
                     const int yn = rc + 1 >= P.ny ? rc + 1 - P.ny : rc + 1;   // periodic wrap
                     const int ys = rc == 0 ? P.ny - 1 : rc - 1;
-                    const unsigned bc = boff(x, rc), bn = boff(x, yn), bs = boff(x, ys);
-                    stf(Bf[2], bn, fs[2]);
-                    stf(Bf[4], bs, fs[4]);
-                    stf(Bg[2], bn, h[2] + P.omq * s_g[2][sn][jm]);
-                    stf(Bg[4], bs, h[4] + P.omq * s_g[4][ss][jm]);
+                    float* Bc = brow(rc);
+                    float* Bn = brow(yn);
+                    float* Bs = brow(ys);
+                    stf(Bn, boff(2, x), fs[2]);
+                    stf(Bs, boff(4, x), fs[4]);
+                    stf(Bn, boff(11, x), h[2] + P.omq * s_g[2][sn][jm]);
+                    stf(Bs, boff(13, x), h[4] + P.omq * s_g[4][ss][jm]);
                     if (lane >= 1) {                       // pusher x-1 is in this wave
-                        stf(Bf[1], bc, l1);
-                        stf(Bf[5], bn, l5);
-                        stf(Bf[8], bs, l8);
-                        stf(Bg[1], bc, lh1 + P.omq * s_g[1][sc][jm]);
+                        stf(Bc, boff(1, x), l1);
+                        stf(Bn, boff(5, x), l5);
+                        stf(Bs, boff(8, x), l8);
+                        stf(Bc, boff(10, x), lh1 + P.omq * s_g[1][sc][jm]);
                     }
                     if (lane < 63 && t + 1 < wv) {         // pusher x+1 is in this wave
-                        stf(Bf[3], bc, r3);
-                        stf(Bf[6], bn, r6);
-                        stf(Bf[7], bs, r7);
-                        stf(Bg[3], bc, rh3 + P.omq * s_g[3][sc][jm]);
+                        stf(Bc, boff(3, x), r3);
+                        stf(Bn, boff(6, x), r6);
+                        stf(Bs, boff(7, x), r7);
+                        stf(Bc, boff(12, x), rh3 + P.omq * s_g[3][sc][jm]);
                     }
                     // the lanes at the wave edges store across them
                     if (lane == 63 || t + 1 >= wv) {
                         const int xe = wrapx(x + 1, P.nx);
-                        stf(Bf[1], boff(xe, rc), fs[1]);
-                        stf(Bf[5], boff(xe, yn), fs[5]);
-                        stf(Bf[8], boff(xe, ys), fs[8]);
-                        stf(Bg[1], boff(xe, rc), h[1] + P.omq * s_g[1][sc][jm + 1]);
+                        stf(Bc, boff(1, xe), fs[1]);
+                        stf(Bn, boff(5, xe), fs[5]);
+                        stf(Bs, boff(8, xe), fs[8]);
+                        stf(Bc, boff(10, xe), h[1] + P.omq * s_g[1][sc][jm + 1]);
                     }
                     if (lane == 0) {
                         const int xw = wrapx(x - 1, P.nx);
-                        stf(Bf[3], boff(xw, rc), fs[3]);
-                        stf(Bf[6], boff(xw, yn), fs[6]);
-                        stf(Bf[7], boff(xw, ys), fs[7]);
-                        stf(Bg[3], boff(xw, rc), h[3] + P.omq * s_g[3][sc][jm - 1]);
+                        stf(Bc, boff(3, xw), fs[3]);
+                        stf(Bn, boff(6, xw), fs[6]);
+                        stf(Bs, boff(7, xw), fs[7]);
+                        stf(Bc, boff(12, xw), h[3] + P.omq * s_g[3][sc][jm - 1]);
                     }
                 }
             } else {
@@ -833,7 +836,7 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
                 };
                 auto mask_rel = [&](int dy, int dx) { return s_m[(rc + dy) & (RING - 1)][jm + dx]; };
                 if (own_fluid) {
-                    const StreamCtx c{&P, B, x, rc, (unsigned)rc * P.pitch + x};
+                    const StreamCtx c{&P, B, x, rc};
                     stream_one<2, false>(c, fs[2], 0.f, 0.f, [&]() { return mask_rel(1, 0); }, open_fluid);
                     stream_one<4, false>(c, fs[4], 0.f, 0.f, [&]() { return mask_rel(-1, 0); }, open_fluid);
                     stream_one<2, true>(c, h[2], s_g[2][sn][jm], s_g[4][sc][jm], [&]() { return mask_rel(1, 0); },
@@ -866,9 +869,9 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
         {
             const int rf2 = rc + 2 * dir;
             const int rcl = min(max(rf2, y0), y1 - 1);
-            const unsigned bo = boff(xc, rcl);
+            const float* Ar = arow(rcl);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) rf[S][i] = ldf(Af[i], bo);
+            for (int i = 0; i < 9; ++i) rf[S][i] = ldf(Ar, boff(i, xc));
         }
         // the ring slot of row rr - 3 dir is reused next: with one wave the
         // wave barrier keeps the compiler from moving the next row's LDS
@@ -888,6 +891,173 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
     for (int kk = 0; kk < nk; kk += 2) {
         body(std::integral_constant<int, 0>{}, kk);
         body(std::integral_constant<int, 1>{}, kk + 1);
+    }
+}
+
+// A double held by lane - 1 (from_left) or lane + 1 (from_right): DPP wave
+// shifts of both halves; the lane at the wave edge gets its own value back.
+__device__ __forceinline__ double dfrom_left(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double dfrom_right(double v)
+{
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+}
+
+// Plain rows without a walk: the row kernel.  Each wave updates the 64
+// columns of one row of one piece on its own (no LDS, no barrier).  A plain
+// row has no solid node in rows y-1..y+1 of its strip and halo and no open
+// row within reach, so phi~ is the raw phi = sum g of those rows and every
+// population streams to a fluid node.  Each lane loads f of its node and g
+// (with the g_0 remainder) of its column in rows y-1, y, y+1; the stencil
+// takes the neighbouring columns' phi by lane shifts, and the edge lanes
+// take the halo columns (x0 - 1 and the column past the piece), which the
+// wave reads with uniform (scalar) loads.  Streaming is that of the walked
+// kernel's plain rows (aligned stores: lane shifts hand the x-moving
+// populations to the lane that owns the destination column); the edge lanes
+// store across the piece edge with the halo column's old g.  The rows above
+// and below are read again by the waves of those rows at about the same
+// time, so the halo rows come from the cache: per node the kernel moves the
+// 14 populations in and out once.  Workgroups are numbered row-major (strip
+// fastest), the order in which the populations of a row lie in memory; a
+// workgroup of NW waves covers a strip of 64 NW columns.
+template <int NW, bool SAMPLE>
+__global__ __launch_bounds__(64 * NW) void k_collide_rows(KParams P, const float* __restrict__ A,
+                                                          float* __restrict__ B,
+                                                          const uint8_t* __restrict__ plain_rows, int n_strips,
+                                                          int y_first, DiagRow* __restrict__ parts)
+{
+    const int y = y_first + (int)(blockIdx.x / (unsigned)n_strips);
+    const int strip = (int)(blockIdx.x - (unsigned)(y - y_first) * (unsigned)n_strips);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int x0 = (strip * NW + wave) * 64;   // first column of this wave's piece (uniform)
+    if (y >= P.ny || x0 >= P.nx || !plain_rows[(size_t)strip * P.ny + y]) return;   // uniform over the wave
+    const int wv = min(64, P.nx - x0);
+    const bool active = lane < wv;
+    const int x = x0 + lane;
+    const int xc = active ? x : P.nx - 1;   // lanes past the edge load the last column (unused)
+    const int ys = y == 0 ? P.ny - 1 : y - 1, yn = y + 1 == P.ny ? 0 : y + 1;   // periodic (plain rows)
+    const int xl = x0 == 0 ? P.nx - 1 : x0 - 1;                // halo columns (uniform)
+    const int xr = x0 + wv == P.nx ? 0 : x0 + wv;
+
+    // population rows of the three lattice rows (uniform bases), one lane offset
+    const float* As = A + (size_t)(unsigned)ys * P.rs;
+    const float* Ac = A + (size_t)(unsigned)y * P.rs;
+    const float* An = A + (size_t)(unsigned)yn * P.rs;
+    const uint16_t* Alo = lo_plane(A, P);
+    const unsigned pch = (unsigned)P.pitch;
+    // 32-bit byte offset of this lane's column (one per lane, shared by every
+    // access); the population rows are uniform bases
+    const unsigned xo = (unsigned)xc << 2, xo2 = (unsigned)xc << 1;
+    auto ldf = [](const float* base, unsigned bo) { return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + bo); };
+    auto ldh = [](const uint16_t* base, unsigned bo) { return *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(base) + bo); };
+    float f[9], gs[5], gc[5], gn[5];
+    uint16_t los, loc, lon;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = ldf(Ac + i * pch, xo);
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        gs[i] = ldf(As + (9 + i) * pch, xo);
+        gc[i] = ldf(Ac + (9 + i) * pch, xo);
+        gn[i] = ldf(An + (9 + i) * pch, xo);
+    }
+    los = ldh(Alo + (size_t)(unsigned)ys * pch, xo2);
+    loc = ldh(Alo + (size_t)(unsigned)y * pch, xo2);
+    lon = ldh(Alo + (size_t)(unsigned)yn * pch, xo2);
+    // halo columns: uniform addresses
+    auto halo_phi = [&](const float* R, int yy, int hx) {
+        return phi_of(R[9 * pch + hx], R[10 * pch + hx], R[11 * pch + hx], R[12 * pch + hx], R[13 * pch + hx],
+                      bf16_to_float(Alo[(unsigned)yy * pch + hx]));
+    };
+    const double pls = halo_phi(As, ys, xl), plc = halo_phi(Ac, y, xl), pln = halo_phi(An, yn, xl);
+    const double prs = halo_phi(As, ys, xr), prc = halo_phi(Ac, y, xr), prn = halo_phi(An, yn, xr);
+    const float g1r = Ac[10 * pch + xr];   // pre-collision g_1 of the column past the piece, row y
+    const float g3l = Ac[12 * pch + xl];   // pre-collision g_3 of the column before it
+
+    const double ps = phi_of(gs[0], gs[1], gs[2], gs[3], gs[4], bf16_to_float(los));
+    const double pc = phi_of(gc[0], gc[1], gc[2], gc[3], gc[4], bf16_to_float(loc));
+    const double pn = phi_of(gn[0], gn[1], gn[2], gn[3], gn[4], bf16_to_float(lon));
+    const bool ledge = lane == 0, redge = lane == wv - 1;
+    double st[9];
+    st[0] = pc;
+    st[2] = pn;
+    st[4] = ps;
+    {
+        const double l_s = dfrom_left(ps), l_c = dfrom_left(pc), l_n = dfrom_left(pn);
+        const double r_s = dfrom_right(ps), r_c = dfrom_right(pc), r_n = dfrom_right(pn);
+        st[1] = redge ? prc : r_c;
+        st[3] = ledge ? plc : l_c;
+        st[5] = redge ? prn : r_n;
+        st[6] = ledge ? pln : l_n;
+        st[7] = ledge ? pls : l_s;
+        st[8] = redge ? prs : r_s;
+    }
+
+    float fs[9], h[5], g0h = 0.f;
+    uint16_t g0l = 0;
+    SampleTerms dterm;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fs[i] = 0.f;
+#pragma unroll
+    for (int i = 0; i < 5; ++i) h[i] = 0.f;
+    if (active) {
+        Macro mac;
+        node_collide(P, f, gc, bf16_to_float(loc), st, y < P.force_rows ? P.fb : 0.f, fs, h, g0h, g0l, mac);
+        if constexpr (SAMPLE) sample_node(mac, y >= P.diag_row0, dterm);
+    }
+    // the populations moving in x come from the neighbouring lanes
+    const float l1 = from_left(fs[1]), l5 = from_left(fs[5]), l8 = from_left(fs[8]);
+    const float lh1 = from_left(h[1]);
+    const float r3 = from_right(fs[3]), r6 = from_right(fs[6]), r7 = from_right(fs[7]);
+    const float rh3 = from_right(h[3]);
+    if (active) {
+        auto stf = [](float* base, unsigned bo, float v) { *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + bo) = v; };
+        float* Bs = B + (size_t)(unsigned)ys * P.rs;
+        float* Bc = B + (size_t)(unsigned)y * P.rs;
+        float* Bn = B + (size_t)(unsigned)yn * P.rs;
+        const unsigned wo = (unsigned)x << 2;
+        stf(Bc, wo, fs[0]);
+        stf(Bc + 9 * pch, wo, g0h);
+        *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lo_plane(B, P) + (size_t)(unsigned)y * pch) + ((unsigned)x << 1)) = g0l;
+        stf(Bn + 2 * pch, wo, fs[2]);
+        stf(Bs + 4 * pch, wo, fs[4]);
+        stf(Bn + 11 * pch, wo, h[2] + P.omq * gn[2]);
+        stf(Bs + 13 * pch, wo, h[4] + P.omq * gs[4]);
+        if (!ledge) {                          // pusher x-1 is in this wave
+            stf(Bc + 1 * pch, wo, l1);
+            stf(Bn + 5 * pch, wo, l5);
+            stf(Bs + 8 * pch, wo, l8);
+            stf(Bc + 10 * pch, wo, lh1 + P.omq * gc[1]);
+        } else {                               // lane 0 stores across the left edge
+            const unsigned lo_ = (unsigned)xl << 2;
+            stf(Bc + 3 * pch, lo_, fs[3]);
+            stf(Bn + 6 * pch, lo_, fs[6]);
+            stf(Bs + 7 * pch, lo_, fs[7]);
+            stf(Bc + 12 * pch, lo_, h[3] + P.omq * g3l);
+        }
+        if (!redge) {                          // pusher x+1 is in this wave
+            stf(Bc + 3 * pch, wo, r3);
+            stf(Bn + 6 * pch, wo, r6);
+            stf(Bs + 7 * pch, wo, r7);
+            stf(Bc + 12 * pch, wo, rh3 + P.omq * gc[3]);
+        } else {                               // the last lane stores across the right edge
+            const unsigned ro_ = (unsigned)xr << 2;
+            stf(Bc + 1 * pch, ro_, fs[1]);
+            stf(Bn + 5 * pch, ro_, fs[5]);
+            stf(Bs + 8 * pch, ro_, fs[8]);
+            stf(Bc + 10 * pch, ro_, h[1] + P.omq * g1r);
+        }
+    }
+    if constexpr (SAMPLE) {
+        // this wave's 64 columns of row y are piece x0 / 64
+        const DiagRow r = sample_piece(dterm);
+        if (lane == 0) parts[(size_t)(x0 >> 6) * P.ny + y] = r;
     }
 }
 
@@ -981,9 +1151,9 @@ __global__ void k_init_eq(KParams P, float* __restrict__ A, const uint8_t* __res
         node_equilibrium(P, ph, mu, ux ? ux[kin] : 0.f, uy ? uy[kin] : 0.f, fe, ge, g0l);
     }
 #pragma unroll
-    for (int i = 0; i < 9; ++i) A[(size_t)i * P.plane + k] = fe[i];
+    for (int i = 0; i < 9; ++i) A[pidx(P, i, x, y)] = fe[i];
 #pragma unroll
-    for (int i = 0; i < 5; ++i) A[(size_t)(9 + i) * P.plane + k] = ge[i];
+    for (int i = 0; i < 5; ++i) A[pidx(P, 9 + i, x, y)] = ge[i];
     lo_plane(A, P)[k] = g0l;
 }
 
@@ -1002,7 +1172,7 @@ __global__ void k_moments(KParams P, const float* __restrict__ A, const uint8_t*
         float f[9];
         double st[9], Fx, Fy;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = A[(size_t)i * P.plane + k];
+        for (int i = 0; i < 9; ++i) f[i] = A[pidx(P, i, x, y)];
         load_stencil(P, phi, x, y, st);
         Macro m;
         node_macro(P, f, st, y < P.force_rows ? P.fb : 0.f, m, Fx, Fy);
@@ -1035,7 +1205,7 @@ __global__ void k_state_io(KParams P, float* __restrict__ A, const uint8_t* __re
     const float w[9] = {4.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f,
                         1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
     const unsigned kp = (unsigned)y * P.pitch + x;
-    const size_t k = (size_t)(is_f ? i : 9 + i) * P.plane + kp;
+    const size_t k = pidx(P, is_f ? i : 9 + i, x, y);
     const size_t ke = (size_t)i * P.nx * P.ny + (size_t)y * P.nx + x;
     uint16_t* lo = lo_plane(A, P);
     if (is_f) {
@@ -1089,7 +1259,7 @@ __device__ __forceinline__ void diag_row(const KParams& P, float fb, const float
                     float f[9];
                     double st[9], Fx, Fy;
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) f[i] = A[(size_t)i * P.plane + kk];
+                    for (int i = 0; i < 9; ++i) f[i] = A[pidx(P, i, x, y)];
                     load_stencil(P, phi, x, y, st);
                     Macro m;
                     node_macro(P, f, st, y < P.force_rows ? fb : 0.f, m, Fx, Fy);
@@ -1426,7 +1596,25 @@ hipError_t launch_collide_fused_t(const KParams& P, const float* A, float* B, co
     const int bw = 64 * waves_x;
     const int n_strips = (P.nx + bw - 1) / bw;
     const int n_rb = (P.ny + rows_per_block - 1) / rows_per_block;
-    if (n_plain_tiles < 0) {   // every tile
+    if (rows_per_block == 1) {   // one row per workgroup, no walk: the row kernel
+        const dim3 grid((unsigned)n_strips * (unsigned)P.ny);
+        switch (waves_x) {
+        case 1:
+            hipLaunchKernelGGL((k_collide_rows<1, SAMPLE>), grid, dim3(64), 0, st, P, A, B, plain_rows, n_strips, 0,
+                               parts);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_collide_rows<2, SAMPLE>), grid, dim3(128), 0, st, P, A, B, plain_rows, n_strips,
+                               0, parts);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_collide_rows<4, SAMPLE>), grid, dim3(256), 0, st, P, A, B, plain_rows, n_strips,
+                               0, parts);
+            break;
+        default:
+            return hipErrorInvalidValue;
+        }
+    } else if (n_plain_tiles < 0) {   // every tile
         const dim3 grid(n_strips * n_rb);
         switch (waves_x) {
         case 1:

@@ -21,7 +21,7 @@ def test_paper_preset_matches_oracle(oracle_mod, gpu_lib):
     for t in (100, 300, 600):
         o.step(t - o.t)
         g.step(t - g.t)
-        for k, v in _compare_fields(o, g, 1e-5, elementwise=True).items():
+        for k, v in _compare_fields(o, g, 1e-5).items():
             worst[k] = max(worst.get(k, 0.0), v)
     print("worst relative L2:", worst)
 
