@@ -129,8 +129,8 @@ const char *ij_last_error(const ij_sim *s);
 
 /* Bytes of ONE distribution buffer for the given parameters: for each
  * lattice row, 14 rows of floats with a 64-float aligned pitch (9 f, 5 g:
- * the populations of one lattice row are stored together), then one 16-bit
- * plane [ny][pitch] (low-order part of g_0). */
+ * the populations of one lattice row are stored together) followed by one
+ * row of 16-bit words (low-order part of g_0). */
 ij_status ij_required_bytes(const ij_params *p, size_t *bytes);
 
 /* Use caller-owned device buffers (each >= ij_required_bytes, 256-byte
@@ -189,10 +189,10 @@ ij_status ij_set_state(ij_sim *s, const float *f_dev, const float *g_dev, int64_
 
 /* Checkpoint and bit-exact resume of the state the update works on (Eqs. 3
  * and 8 advance f and g alone; the pulse phase of Fig. 1 follows from the
- * step counter).  The blob is a 64-byte header (magic "IJSTATE2", lattice
+ * step counter).  The blob is a 64-byte header (magic "IJSTATE3", lattice
  * size, row pitch, step counter, a hash of the wall mask, payload size)
  * followed by the current distribution buffer exactly as the kernels store
- * it: the shifted f planes, the g planes and the 16-bit remainder plane of
+ * it: the shifted f, the g and the 16-bit remainder of
  * g_0.  ij_state_bytes gives its size (64 + ij_required_bytes).
  * ij_save_state writes it to caller host memory of at least that size.
  * ij_load_state restores it into a handle with the same lattice size and

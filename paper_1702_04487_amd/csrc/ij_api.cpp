@@ -131,7 +131,7 @@ void fill_kparams(ij_sim* s)
     K.force_rows = (int)std::min<int64_t>(p.force_rows, s->ny);
     K.diag_row0 = (int)p.diag_row0;
     K.plane = (unsigned)s->plane;
-    K.rs = (unsigned)(ij::kFloatPlanes * s->pitch);
+    K.rs = (unsigned)(ij::kFloatPlanes * s->pitch + s->pitch / 2);   // 14 float rows and one 16-bit row
     K.phi_star = s->phi_star;
     K.beta4 = 4.0 * s->beta;
     K.kappa = s->kappa;
@@ -683,7 +683,7 @@ ij_status ij_save_state(ij_sim* s, void* blob, size_t bytes, void* stream)
         if (r != IJ_OK) return r;
     }
     StateHeader h{};
-    std::memcpy(h.magic, "IJSTATE2", 8);
+    std::memcpy(h.magic, "IJSTATE3", 8);
     h.nx = s->nx;
     h.ny = s->ny;
     h.nz = 1;
@@ -704,7 +704,7 @@ ij_status ij_load_state(ij_sim* s, const void* blob, size_t bytes, void* stream)
     StateHeader h;
     std::memcpy(&h, blob, sizeof h);
     const size_t payload = buffer_bytes(s->plane);
-    if (std::memcmp(h.magic, "IJSTATE2", 8) != 0) return fail(s, IJ_ERR_INVALID_ARG, "not a checkpoint of this library");
+    if (std::memcmp(h.magic, "IJSTATE3", 8) != 0) return fail(s, IJ_ERR_INVALID_ARG, "not a checkpoint of this library");
     if (h.nx != s->nx || h.ny != s->ny || h.nz != 1 || h.pitch != s->pitch || h.payload != payload)
         return fail(s, IJ_ERR_INVALID_ARG, "checkpoint of a different lattice size");
     if (h.wall_hash != fnv1a(s->wall_host.data(), s->wall_host.size()))

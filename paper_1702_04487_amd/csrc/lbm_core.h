@@ -6,11 +6,11 @@
 
 namespace ij {
 
-// Buffer layout: per lattice row, 14 consecutive rows of pitch floats
-// (f_0..f_8 shifted by w_i n0, then g_0..g_4), so population i of node
-// (x, y) is at (14 y + i) pitch + x; after the ny such row groups, one plane
-// [ny][pitch] of 16-bit words holding the bfloat16 remainder g_0 - float(g_0)
-// of the rest order-parameter population.
+// Buffer layout: per lattice row, a block of 14 rows of pitch floats (f_0..f_8
+// shifted by w_i n0, then g_0..g_4) and one row of pitch 16-bit words holding
+// the bfloat16 remainder g_0 - float(g_0) of the rest order-parameter
+// population; population i of node (x, y) is at y rs + i pitch + x with
+// rs = 14.5 pitch floats.
 constexpr int kFloatPlanes = 14;
 constexpr int kMaxRowsPerBlock = 1024;   // rows of one tile (LDS row flags)
 
@@ -23,8 +23,8 @@ struct KParams {
     int force_rows;       // body force on fluid nodes with y < force_rows
     int diag_row0;        // rows y >= diag_row0 count ink in a diagnostics sample
     unsigned plane;       // nodes of a padded lattice (ny * pitch): the size of the
-                          // g_0 remainder plane, the wall mask and the phi field
-    unsigned rs;          // floats per lattice row of a buffer (14 * pitch)
+                          // wall mask and the phi field
+    unsigned rs;          // floats per lattice row of a buffer (14.5 * pitch)
     // double-precision order-parameter constants
     double phi_star, beta4, kappa, gamma, omega_phi, inv_width;
     double wet[4];        // ghost offset 2 Omega phi*/W per wall class (index 1, 2)

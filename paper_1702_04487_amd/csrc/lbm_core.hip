@@ -2,18 +2,18 @@
 // (arXiv:1702.04487, Methods Eqs. 3-10; actuation of Fig. 1; wetting walls and
 // "fully developed" rows of Results, "Reproducing the experiment").
 //
-// Storage: one buffer = 14 float populations per node, then one 16-bit plane.
-// The populations of one lattice row are 14 consecutive rows of pitch floats
-// (pitch = nx rounded up to 64): population i of node (x, y) sits at
-// (14 y + i) pitch + x, so a row's populations are one contiguous region
-// (one stream of memory per lattice row, not 14 streams planes apart):
+// Storage: one buffer holds, for each lattice row y, a block of 14 rows of
+// pitch floats (pitch = nx rounded up to 64) and then one row of pitch
+// 16-bit words; the block of row y starts at float y * rs, rs = 14.5 pitch.
+// Population i of node (x, y) sits at y rs + i pitch + x, so everything a
+// lattice row holds is one contiguous region of memory (one stream per
+// lattice row, not 15 streams planes apart):
 //   i = 0..8      f_i - w_i n0 (D2Q9 distributions shifted by their rest
 //                 value, which keeps the low-order bits of the small velocity
 //                 signal in FP32);
 //   i = 9..13     g_0..g_4 (D2Q5);
-//   16-bit plane  [ny][pitch] bfloat16 of g_0 - float(g_0): g_0 carries
-//                 +-phi* and is the only population whose FP32 rounding would
-//                 quantise phi.
+//   16-bit row    bfloat16 of g_0 - float(g_0): g_0 carries +-phi* and is the
+//                 only population whose FP32 rounding would quantise phi.
 // Two buffers A (current, pre-collision) and B (next) alternate.
 //
 // Velocities c_0=(0,0) c_1=(1,0) c_2=(0,1) c_3=(-1,0) c_4=(0,-1)
@@ -232,13 +232,14 @@ __device__ __forceinline__ size_t pidx(const KParams& P, int i, int x, int y)
     return (size_t)(unsigned)y * P.rs + (unsigned)(i * P.pitch + x);
 }
 
-__device__ __forceinline__ const uint16_t* lo_plane(const float* A, const KParams& P)
+// the 16-bit g_0 remainders of lattice row y (after its 14 float rows)
+__device__ __forceinline__ const uint16_t* lo_row(const float* A, const KParams& P, int y)
 {
-    return reinterpret_cast<const uint16_t*>(A + (size_t)kFloatPlanes * P.plane);
+    return reinterpret_cast<const uint16_t*>(A + (size_t)(unsigned)y * P.rs + (size_t)kFloatPlanes * P.pitch);
 }
-__device__ __forceinline__ uint16_t* lo_plane(float* A, const KParams& P)
+__device__ __forceinline__ uint16_t* lo_row(float* A, const KParams& P, int y)
 {
-    return reinterpret_cast<uint16_t*>(A + (size_t)kFloatPlanes * P.plane);
+    return reinterpret_cast<uint16_t*>(A + (size_t)(unsigned)y * P.rs + (size_t)kFloatPlanes * P.pitch);
 }
 
 // Direction table of the streaming step.
@@ -360,7 +361,7 @@ __device__ __forceinline__ void phi_node(const KParams& P, const float* __restri
     const unsigned k = (unsigned)y * P.pitch + x;
     if (wall[k]) return;
     phi[k] = phi_of(A[pidx(P, 9, x, y)], A[pidx(P, 10, x, y)], A[pidx(P, 11, x, y)], A[pidx(P, 12, x, y)],
-                    A[pidx(P, 13, x, y)], bf16_to_float(lo_plane(A, P)[k]));
+                    A[pidx(P, 13, x, y)], bf16_to_float(lo_row(A, P, y)[x]));
 }
 
 __global__ void k_phi_from_g(KParams P, const float* __restrict__ A, const uint8_t* __restrict__ wall,
@@ -434,7 +435,7 @@ __global__ void k_collide_ref(KParams P, const float* __restrict__ A, float* __r
     for (int i = 0; i < 9; ++i) f[i] = A[pidx(P, i, x, y)];
 #pragma unroll
     for (int i = 0; i < 5; ++i) g[i] = A[pidx(P, 9 + i, x, y)];
-    const float lo = bf16_to_float(lo_plane(A, P)[k]);
+    const float lo = bf16_to_float(lo_row(A, P, y)[x]);
     load_stencil(P, phi, x, y, st);
     Macro m;
     float g0h;
@@ -443,7 +444,7 @@ __global__ void k_collide_ref(KParams P, const float* __restrict__ A, float* __r
 
     B[pidx(P, 0, x, y)] = fs[0];
     B[pidx(P, 9, x, y)] = g0h;
-    lo_plane(B, P)[k] = g0l;
+    lo_row(B, P, y)[x] = g0l;
     const StreamCtx c{&P, B, x, y};
     auto open_fluid = [&](int top, int dx) {
         const int cx = wrapx(x + dx, P.nx);
@@ -617,8 +618,6 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
 
     // row bases (uniform over the workgroup: 64-bit) and 32-bit byte offsets
     // of population i of column xx within a row
-    const uint16_t* Alo = lo_plane(A, P);
-    uint16_t* Blo = lo_plane(B, P);
     auto arow = [&](int yy) { return A + (size_t)(unsigned)yy * P.rs; };
     auto brow = [&](int yy) { return B + (size_t)(unsigned)yy * P.rs; };
     auto boff = [&](int i, int xx) -> unsigned { return ((unsigned)i * (unsigned)P.pitch + (unsigned)xx) << 2; };
@@ -658,8 +657,8 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
         for (int i = 0; i < 5; ++i) g[i] = ldf(Ar, boff(9 + i, xc));
 #pragma unroll
         for (int i = 0; i < 5; ++i) gh[i] = ldf(Ar, boff(9 + i, hx));
-        lo = Alo[k];
-        loh = Alo[kh];
+        lo = lo_row(A, P, ry)[xc];
+        loh = lo_row(A, P, ry)[hx];
     };
 
     // rows y0-2 .. y1+1 pass through the ring, upwards, or downwards when
@@ -773,7 +772,7 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
                 float* Bc = brow(rc);
                 stf(Bc, boff(0, x), fs[0]);
                 stf(Bc, boff(9, x), g0h);
-                Blo[(unsigned)rc * P.pitch + x] = g0l;
+                lo_row(B, P, rc)[x] = g0l;
                 if constexpr (!PLAIN) {
 #pragma unroll
                     for (int i = 1; i < 9; ++i) s_out[i - 1][jo] = fs[i];
@@ -950,7 +949,6 @@ __global__ __launch_bounds__(64 * NW) void k_collide_rows(KParams P, const float
     const float* As = A + (size_t)(unsigned)ys * P.rs;
     const float* Ac = A + (size_t)(unsigned)y * P.rs;
     const float* An = A + (size_t)(unsigned)yn * P.rs;
-    const uint16_t* Alo = lo_plane(A, P);
     const unsigned pch = (unsigned)P.pitch;
     // 32-bit byte offset of this lane's column (one per lane, shared by every
     // access); the population rows are uniform bases
@@ -967,13 +965,13 @@ __global__ __launch_bounds__(64 * NW) void k_collide_rows(KParams P, const float
         gc[i] = ldf(Ac + (9 + i) * pch, xo);
         gn[i] = ldf(An + (9 + i) * pch, xo);
     }
-    los = ldh(Alo + (size_t)(unsigned)ys * pch, xo2);
-    loc = ldh(Alo + (size_t)(unsigned)y * pch, xo2);
-    lon = ldh(Alo + (size_t)(unsigned)yn * pch, xo2);
+    los = ldh(lo_row(A, P, ys), xo2);
+    loc = ldh(lo_row(A, P, y), xo2);
+    lon = ldh(lo_row(A, P, yn), xo2);
     // halo columns: uniform addresses
     auto halo_phi = [&](const float* R, int yy, int hx) {
         return phi_of(R[9 * pch + hx], R[10 * pch + hx], R[11 * pch + hx], R[12 * pch + hx], R[13 * pch + hx],
-                      bf16_to_float(Alo[(unsigned)yy * pch + hx]));
+                      bf16_to_float(lo_row(A, P, yy)[hx]));
     };
     const double pls = halo_phi(As, ys, xl), plc = halo_phi(Ac, y, xl), pln = halo_phi(An, yn, xl);
     const double prs = halo_phi(As, ys, xr), prc = halo_phi(Ac, y, xr), prn = halo_phi(An, yn, xr);
@@ -1024,7 +1022,7 @@ __global__ __launch_bounds__(64 * NW) void k_collide_rows(KParams P, const float
         const unsigned wo = (unsigned)x << 2;
         stf(Bc, wo, fs[0]);
         stf(Bc + 9 * pch, wo, g0h);
-        *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lo_plane(B, P) + (size_t)(unsigned)y * pch) + ((unsigned)x << 1)) = g0l;
+        *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lo_row(B, P, y)) + ((unsigned)x << 1)) = g0l;
         stf(Bn + 2 * pch, wo, fs[2]);
         stf(Bs + 4 * pch, wo, fs[4]);
         stf(Bn + 11 * pch, wo, h[2] + P.omq * gn[2]);
@@ -1154,7 +1152,7 @@ __global__ void k_init_eq(KParams P, float* __restrict__ A, const uint8_t* __res
     for (int i = 0; i < 9; ++i) A[pidx(P, i, x, y)] = fe[i];
 #pragma unroll
     for (int i = 0; i < 5; ++i) A[pidx(P, 9 + i, x, y)] = ge[i];
-    lo_plane(A, P)[k] = g0l;
+    lo_row(A, P, y)[x] = g0l;
 }
 
 // n, phi, u at every node (0 at solids) into caller arrays [ny][nx]
@@ -1204,10 +1202,9 @@ __global__ void k_state_io(KParams P, float* __restrict__ A, const uint8_t* __re
     }
     const float w[9] = {4.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f, 1.f / 9.f,
                         1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
-    const unsigned kp = (unsigned)y * P.pitch + x;
     const size_t k = pidx(P, is_f ? i : 9 + i, x, y);
     const size_t ke = (size_t)i * P.nx * P.ny + (size_t)y * P.nx + x;
-    uint16_t* lo = lo_plane(A, P);
+    uint16_t* lo = lo_row(A, P, y);
     if (is_f) {
         const float shift = w[i] * P.n0;
         if (to_ext)
@@ -1216,10 +1213,10 @@ __global__ void k_state_io(KParams P, float* __restrict__ A, const uint8_t* __re
             A[k] = ext[ke] - shift;
     } else if (i == 0) {
         if (to_ext) {
-            ext[ke] = (float)((double)A[k] + (double)bf16_to_float(lo[kp]));
+            ext[ke] = (float)((double)A[k] + (double)bf16_to_float(lo[x]));
         } else {
             A[k] = ext[ke];
-            lo[kp] = 0;
+            lo[x] = 0;
         }
     } else {
         if (to_ext)
