@@ -309,6 +309,7 @@ ij_status build_plain(ij_sim* s)
     s->strip_x0.resize((size_t)n_strips);
     for (int k = 0; k < n_strips; ++k) s->strip_x0[(size_t)k] = strip_x0(k);
     s->gtiles_host = gt;
+    s->plain_host = plain;
     if (s->plain) (void)hipFree(s->plain);
     if (s->gtiles) (void)hipFree(s->gtiles);
     s->plain = nullptr;

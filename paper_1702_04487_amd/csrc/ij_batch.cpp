@@ -23,7 +23,8 @@ thread_local std::string g_batch_create_error;
 // tile shapes the autotuner times: waves across x, rows per workgroup, and
 // whether the columns past the last full strip go to 64-column strips; each
 // with persistent workgroups and with one workgroup per tile
-const int kCandidates[][3] = {{1, 32, 0}, {2, 32, 0}, {2, 64, 0}, {4, 32, 0}, {4, 64, 0}, {2, 64, 1}, {4, 64, 1}};
+const int kCandidates[][3] = {{1, 32, 0}, {2, 32, 0}, {2, 64, 0}, {4, 32, 0}, {4, 64, 0}, {2, 64, 1}, {4, 64, 1},
+                              {2, 1, 0},  {4, 1, 0}};
 
 // autotuned shapes by batch signature (lattice sizes, walls and diagnostics
 // interval of every case), for the life of the process
@@ -137,9 +138,16 @@ ij_status set_grids(ij_batch* b)
 // tile lists of the launches from the members' current tilings
 ij_status build_tiles(ij_batch* b)
 {
-    std::vector<int4> lists[3];   // wide, tail, general
+    std::vector<int4> lists[4];   // wide, tail, general, rows
     for (size_t c = 0; c < b->sims.size(); ++c) {
         const ij_sim* s = b->sims[c];
+        if (b->rows_per_block == 1) {
+            // row tiles: every plain (row, strip) of the case, row-major
+            for (int y = 0; y < s->ny; ++y)
+                for (int k = 0; k < s->n_strips; ++k)
+                    if (s->plain_host[(size_t)k * s->ny + y])
+                        lists[3].push_back(make_int4((int)c, y, s->strip_x0[(size_t)k], 0));
+        } else
         // plain tiles that hold a plain row (a block of rows that all sit
         // beside solid nodes, such as a nozzle channel, is the general
         // launch's alone)
@@ -161,10 +169,11 @@ ij_status build_tiles(ij_batch* b)
     }
     std::vector<int4> all;
     for (auto& l : lists) all.insert(all.end(), l.begin(), l.end());
-    const int counts[3] = {(int)lists[0].size(), (int)lists[1].size(), (int)lists[2].size()};
+    const int counts[4] = {(int)lists[0].size(), (int)lists[1].size(), (int)lists[2].size(), (int)lists[3].size()};
     const bool same = all.size() == b->tiles_host.size() &&
                       std::memcmp(all.data(), b->tiles_host.data(), all.size() * sizeof(int4)) == 0 &&
-                      counts[0] == b->T.n_wide && counts[1] == b->T.n_tail && counts[2] == b->T.n_gen;
+                      counts[0] == b->T.n_wide && counts[1] == b->T.n_tail && counts[2] == b->T.n_gen &&
+                      counts[3] == b->T.n_rows;
     if (same && (b->d_tiles || all.empty())) return set_grids(b);
     if (all.size() > b->cap_tiles) {
         if (b->d_tiles) (void)hipFree(b->d_tiles);
@@ -180,9 +189,11 @@ ij_status build_tiles(ij_batch* b)
     T.wide = b->d_tiles;
     T.tail = T.wide + counts[0];
     T.gen = T.tail + counts[1];
+    T.rows = T.gen + counts[2];
     T.n_wide = counts[0];
     T.n_tail = counts[1];
     T.n_gen = counts[2];
+    T.n_rows = counts[3];
     drop_graph(b);
     return set_grids(b);
 }
@@ -370,6 +381,7 @@ std::vector<int64_t> signature(const ij_batch* b)
 
 ij_status apply_tiling(ij_batch* b, int waves_x, int rows, int mixed, int persistent)
 {
+    if (rows == 1) mixed = 0;   // a row tile's waves run to the case's edge: no tail strips
     for (ij_sim* s : b->sims) {
         s->waves_x = waves_x;
         s->rows_per_block = rows;

@@ -63,6 +63,7 @@ struct ij_sim {
     int n_ptiles = -1;                 // their count; -1: the plain launch covers every tile
     int n_gtiles = 0;
     std::vector<int4> gtiles_host;
+    std::vector<uint8_t> plain_host;   // the plain-row table [n_strips][ny] as uploaded
     std::vector<int> strip_x0;         // first column of each strip
     std::vector<uint8_t> tile_plain;   // per (row block, strip) tile: holds a plain row
     int n_strips = 0, n_rb = 0;   // of the plain launch's tiling

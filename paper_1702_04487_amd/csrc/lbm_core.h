@@ -106,9 +106,12 @@ hipError_t launch_diag(const KParams& P, const float* A, const uint8_t* wall, co
 // (one wave); at most kMaxRowsPerBlock rows each.  The plain launches run
 // grid_wide / grid_tail workgroups, each over a contiguous run of tiles (a
 // grid of one workgroup per tile when it equals the tile count).
+// With rows_per_block 1 the plain rows go to row tiles (case, row, first
+// column of a strip of 64 * waves_x columns, 0), one workgroup each, instead
+// of walked plain tiles (n_wide = n_tail = 0).
 struct BatchTiles {
-    const int4 *wide, *tail, *gen;
-    int n_wide, n_tail, n_gen;
+    const int4 *wide, *tail, *gen, *rows;
+    int n_wide, n_tail, n_gen, n_rows;
     int grid_wide, grid_tail;
 };
 hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int64_t* t_dev,

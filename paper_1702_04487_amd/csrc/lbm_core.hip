@@ -925,18 +925,13 @@ __device__ __forceinline__ double dfrom_right(double v)
 // 14 populations in and out once.  Workgroups are numbered row-major (strip
 // fastest), the order in which the populations of a row lie in memory; a
 // workgroup of NW waves covers a strip of 64 NW columns.
-template <int NW, bool SAMPLE>
-__global__ __launch_bounds__(64 * NW) void k_collide_rows(KParams P, const float* __restrict__ A,
-                                                          float* __restrict__ B,
-                                                          const uint8_t* __restrict__ plain_rows, int n_strips,
-                                                          int y_first, DiagRow* __restrict__ parts)
+// One wave: the 64 columns from x0 (< nx) of the plain row y, with the
+// body force fb of the step.
+template <bool SAMPLE>
+__device__ __forceinline__ void collide_row_wave(const KParams& P, float fb, const float* __restrict__ A,
+                                                 float* __restrict__ B, int y, int x0, DiagRow* __restrict__ parts)
 {
-    const int y = y_first + (int)(blockIdx.x / (unsigned)n_strips);
-    const int strip = (int)(blockIdx.x - (unsigned)(y - y_first) * (unsigned)n_strips);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int x0 = (strip * NW + wave) * 64;   // first column of this wave's piece (uniform)
-    if (y >= P.ny || x0 >= P.nx || !plain_rows[(size_t)strip * P.ny + y]) return;   // uniform over the wave
     const int wv = min(64, P.nx - x0);
     const bool active = lane < wv;
     const int x = x0 + lane;
@@ -1006,7 +1001,7 @@ __global__ __launch_bounds__(64 * NW) void k_collide_rows(KParams P, const float
     for (int i = 0; i < 5; ++i) h[i] = 0.f;
     if (active) {
         Macro mac;
-        node_collide(P, f, gc, bf16_to_float(loc), st, y < P.force_rows ? P.fb : 0.f, fs, h, g0h, g0l, mac);
+        node_collide(P, f, gc, bf16_to_float(loc), st, y < P.force_rows ? fb : 0.f, fs, h, g0h, g0l, mac);
         if constexpr (SAMPLE) sample_node(mac, y >= P.diag_row0, dterm);
     }
     // the populations moving in x come from the neighbouring lanes
@@ -1057,6 +1052,20 @@ __global__ __launch_bounds__(64 * NW) void k_collide_rows(KParams P, const float
         const DiagRow r = sample_piece(dterm);
         if (lane == 0) parts[(size_t)(x0 >> 6) * P.ny + y] = r;
     }
+}
+
+template <int NW, bool SAMPLE>
+__global__ __launch_bounds__(64 * NW) void k_collide_rows(KParams P, const float* __restrict__ A,
+                                                          float* __restrict__ B,
+                                                          const uint8_t* __restrict__ plain_rows, int n_strips,
+                                                          int y_first, DiagRow* __restrict__ parts)
+{
+    const int y = y_first + (int)(blockIdx.x / (unsigned)n_strips);
+    const int strip = (int)(blockIdx.x - (unsigned)(y - y_first) * (unsigned)n_strips);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int x0 = (strip * NW + wave) * 64;   // first column of this wave's piece (uniform)
+    if (y >= P.ny || x0 >= P.nx || !plain_rows[(size_t)strip * P.ny + y]) return;   // uniform over the wave
+    collide_row_wave<SAMPLE>(P, P.fb, A, B, y, x0, parts);
 }
 
 // One lattice: the PLAIN launch covers every tile, numbered row-block major
@@ -1502,6 +1511,25 @@ __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __rest
     }
 }
 
+// The plain rows of every case of a batch without a walk: workgroup b takes
+// the row tile (case, row, first column of a strip of 64 NW columns) b of
+// the list, each wave 64 columns of it; waves past the case's last column
+// have nothing to do.  Tiles are listed case by case, row-major.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_batch_rows(const CaseRec* __restrict__ cases,
+                                                        const int4* __restrict__ tiles, int parity,
+                                                        const int64_t* __restrict__ t_dev,
+                                                        const int* __restrict__ active)
+{
+    const int4 tl = tiles[blockIdx.x];   // (case, row, first column, 0)
+    if (!active[tl.x]) return;
+    const CaseRec& R = cases[tl.x];
+    const int x0 = tl.z + 64 * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (x0 >= R.P.nx) return;
+    const KParams P = R.P;
+    collide_row_wave<false>(P, (float)case_pulse(R, *t_dev), R.buf[parity], R.buf[1 - parity], tl.y, x0, nullptr);
+}
+
 __global__ void k_batch_tick(int64_t* t_dev, CaseRec* __restrict__ cases, int n_cases, const int* __restrict__ active)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1718,6 +1746,23 @@ hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int p
         per_wg = grid > 0 ? (n + grid - 1) / grid : 0;
         return per_wg > 0 ? (n + per_wg - 1) / per_wg : 0;
     };
+    if (T.n_rows > 0) {   // row tiles: one workgroup each
+        switch (waves_x) {
+        case 1:
+            hipLaunchKernelGGL((k_batch_rows<1>), dim3(T.n_rows), dim3(64), 0, st, cases, T.rows, parity, t_dev, active);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_batch_rows<2>), dim3(T.n_rows), dim3(128), 0, st, cases, T.rows, parity, t_dev,
+                               active);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_batch_rows<4>), dim3(T.n_rows), dim3(256), 0, st, cases, T.rows, parity, t_dev,
+                               active);
+            break;
+        default:
+            return hipErrorInvalidValue;
+        }
+    }
     int pw = 0, pt = 0;
     const int gw = runs(T.n_wide, T.grid_wide, pw);
     const int gt = runs(T.n_tail, T.grid_tail, pt);
