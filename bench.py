@@ -3,18 +3,23 @@
 
 Workload: the 2048 x 16384 droplet field (seeded discs, radii 8-64, ink area
 >= 25 %, flat wetting wall at 120 deg, tau 0.8 ink / 1.0 ambient).  One step
-is one fused collide-stream launch over the whole lattice; the droplet
+is one collide-stream pass over the whole lattice (a row launch over the
+plain rows, a tile launch over the rows next to walls); the droplet
 diagnostics (mass, momentum, per-row ink profile and segments) run every 50
 steps inside the timed region.  Prints one JSON line:
 
   value      whole-job MLUPS = nx * ny * steps / timed seconds / 1e6
-  roofline   the fused kernel's algorithmic HBM bytes (14 float distributions
-             read and written per fluid node, 112 B) over its mean time per
-             step (its two launches), against the 8 TB/s HBM peak; traffic is
-             the counter-measured HBM bytes of one step
+  roofline   the collide-stream kernels' algorithmic HBM bytes (14 float
+             distributions read and written per fluid node, 112 B) over their
+             mean time per step (both launches), against the 8 TB/s HBM peak;
+             traffic is the counter-measured HBM bytes of one step
+  sweep      cases per hour of the 256-case table, batched vs one at a time,
+             and the surrogate's gain (measured end to end on 96 queries)
   cpu_baseline  the FP64 oracle on a bounded slab of the same workload
 
 Usage: python bench.py [--gpus 1] [--steps 5000] [--warmup 100]
+                       [--no-3d] [--no-sweep] [--no-surrogate] [--no-cpu-baseline]
+                       [--extra single_case,sweep_as_written]
 """
 from __future__ import annotations
 
@@ -196,12 +201,16 @@ def sweep_bench(batched_steps: int = 600, plain_steps: int = 300, plain_every: i
             "timed": {"batched_steps": batched_steps, "plain_cases": len(per_case), "plain_steps": plain_steps}}
 
 
-def surrogate_bench(queries: int = 100000, held: int = 256) -> dict:
+def surrogate_bench(queries: int = 100000, held: int = 256, e2e_queries: int = 96) -> dict:
     """The sweep surrogate on the stored solver cases: train the 4-member
     ensemble (the library's kernels), calibrate its trust threshold on a 10 %
-    split, score it on `held` held-out cases, then answer `queries` new
-    query points with the network where it is trusted and the solver
-    elsewhere.  Solver cost per case: a timed batched run."""
+    split, score it on `held` held-out cases (the breakup / no-breakup call
+    over the answered cases, breakup-time and drop-velocity errors over the
+    answered cases that break up), then answer `queries` new query points
+    with the network where it is trusted.  Measured end to end on
+    `e2e_queries` further query points: the prediction plus a batched solver
+    run of the full horizon for every point the network leaves to it.  The
+    solver alone is costed per case from a timed batched run."""
     import torch
     from paper_1702_04487_amd import surrogate as S
     x, y, horizon, _ = S.load_dataset()
@@ -214,10 +223,9 @@ def surrogate_bench(queries: int = 100000, held: int = 256) -> dict:
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     pc, sc = sur.predict(xt[-ncal:])
-    thr = S.calibrate(sc, *S.errors(pc, yt[-ncal:]))
+    thr = S.calibrate(sc, S.scores(pc, yt[-ncal:], horizon))
     ph, sh = sur.predict(xh)
-    ans = sh <= thr
-    et, ev = S.errors(ph, yh)
+    rep = S.summary(S.scores(ph, yh, horizon), sh <= thr)
     xq = S.sample_inputs(queries, 4242)
     sur.predict(xq)   # warm-up
     torch.cuda.synchronize()
@@ -229,19 +237,31 @@ def surrogate_bench(queries: int = 100000, held: int = 256) -> dict:
     log(f"surrogate: trained in {t_train:.2f} s; answers {aq:.3f} of {queries} queries in {t_pred * 1e3:.2f} ms")
     t_case = S.solver_seconds_per_case(xh, horizon)
     solver_cph = 3600.0 / t_case
-    with_cph = queries * 3600.0 / (t_pred + (1.0 - aq) * queries * t_case)
+    # end to end: predict, then the solver on what the network leaves
+    xe = S.sample_inputs(e2e_queries, 4343)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, se = sur.predict(xe)
+    fall = se > thr
+    if fall.any():
+        S.run_lbm(xe[fall], horizon, progress=False)
+    torch.cuda.synchronize()
+    t_e2e = time.perf_counter() - t0
+    e2e_cph = e2e_queries * 3600.0 / t_e2e
+    log(f"surrogate: end to end {e2e_queries} queries, {int(fall.sum())} to the solver, {t_e2e:.1f} s")
+    modelled_cph = queries * 3600.0 / (t_pred + (1.0 - aq) * queries * t_case)
     return {"cases": "256 x 2048 nozzle (w 32, L 256), 7 sweep inputs, periodic pulse, stable variant, "
                      f"{horizon} steps; {len(x)} stored solver cases ({len(xt) - ncal} train, {ncal} calibrate, "
                      f"{held} held out)",
             "members": 4, "train_seconds": round(t_train, 3), "threshold": thr,
-            "held_out": {"answered": int(ans.sum()), "of": held,
-                         "mean_err_breakup": float(et[ans].mean()) if ans.any() else None,
-                         "mean_err_v_drop": float(ev[ans].mean()) if ans.any() else None},
+            "held_out": rep,
             "queries": queries, "answered_fraction": round(aq, 4), "predict_ms": round(t_pred * 1e3, 3),
             "solver_seconds_per_case": round(t_case, 4),
             "batched_cases_per_hour": round(solver_cph, 1),
-            "batched_surrogate_cases_per_hour": round(with_cph, 1),
-            "gain": round(with_cph / solver_cph, 3)}
+            "end_to_end": {"queries": e2e_queries, "to_solver": int(fall.sum()), "seconds": round(t_e2e, 3),
+                           "cases_per_hour": round(e2e_cph, 1), "gain": round(e2e_cph / solver_cph, 3)},
+            "modelled_cases_per_hour_1e5": round(modelled_cph, 1),
+            "modelled_gain_1e5": round(modelled_cph / solver_cph, 3)}
 
 
 BYTES_PER_NODE_3D = 208   # 19 + 7 float populations read and written per fluid node
@@ -320,6 +340,86 @@ def round_nozzle_3d_bench(steps: int = 300, warmup: int = 20, oracle: bool = Tru
     return out
 
 
+def single_case_bench() -> dict:
+    """The 256 x 2048 single nozzle case (contact angle 60 deg, tau 0.8 / 1.0,
+    pulse +2e-4 x 2000, -1e-4 x 1000, idle to 60000 steps): as written, and
+    with both amplitudes scaled so that the viscous centreline speed of the
+    channel, F w^2 / (8 n0 nu_ink), is 0.35 down to 0.1.  Breakup step, drop
+    velocity and volume (diagnostics every 50 steps), or the step at which
+    the stability guard stopped the run."""
+    import workloads as W
+    from paper_1702_04487_amd import lbm
+    c = W.config_nozzle_single()
+    p0 = dict(c["params"], diag_row0=c["row0"], diag_every=50)
+    w = c["nozzle"][1]
+    bound = max(p0["f_pos"], p0["f_neg"]) * w * w / (8.0 * 0.55 * (0.8 - 0.5) / 3.0)
+    out = {"workload": "256x2048 nozzle, w 32, L 256, theta 60, 60000 steps", "speed_bound_as_written": round(bound, 4)}
+    for name, cap in (("as_written", None), ("scaled_0.35", 0.35), ("scaled_0.3", 0.3), ("scaled_0.25", 0.25),
+                      ("scaled_0.2", 0.2), ("scaled_0.1", 0.1)):
+        k = 1.0 if cap is None else cap / bound
+        p = dict(p0, f_pos=p0["f_pos"] * k, f_neg=p0["f_neg"] * k)
+        sim = lbm.Sim(p, c["wall"])
+        sim.init_distance(W.meniscus_distance(p["nx"], p["ny"], c["row0"]))
+        t0 = time.perf_counter()
+        done = 0
+        while done < c["steps"] and sim.check() == lbm.IJ_OK:
+            n = min(250, c["steps"] - done)
+            sim.step(n)
+            done += n
+        d = sim.diagnostics()
+        secs = time.perf_counter() - t0
+        # a breakup read after the guard tripped is not a result
+        valid = d["breakup_step"] >= 0 and (d["unstable_step"] < 0 or d["breakup_step"] < d["unstable_step"])
+        out[name] = {"f_pos": p["f_pos"], "f_neg": p["f_neg"], "steps": done, "seconds": round(secs, 2),
+                     "unstable_step": d["unstable_step"], "breakup_step": d["breakup_step"] if valid else -1,
+                     "v_drop": d["v_drop"] if valid and d["v_drop"] == d["v_drop"] else None,
+                     "vol_drop": d["vol_drop"] if valid else 0, "satellite": d["satellite"] if valid else 0,
+                     "drop_len": d["drop_len"] if valid else 0}
+        log(f"single case {name}: {out[name]}")
+        sim.close()
+    return out
+
+
+def sweep_as_written_bench(steps: int = 40000) -> dict:
+    """The 256-case sweep table as written (no scaling): the whole batch run
+    for its 40000 steps; the cases the stability guard stops are then run
+    again in their scaled (stable) form as the fallback, and the cases per
+    hour count both runs."""
+    import torch
+    import workloads as W
+    from paper_1702_04487_amd import lbm
+    raw = W.sweep_cases(256, seed=1234, stable=False)
+    stable = W.sweep_cases(256, seed=1234, stable=True)
+
+    def run(cases):
+        b = lbm.Batch([c["params"] for c in cases])
+        for sim in b.cases:
+            sim.init_default()
+        b.autotune(10)
+        b.set_graph(50)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            n = min(10000, steps - done)
+            b.step(n)
+            done += n
+            torch.cuda.synchronize()
+            log(f"sweep as written: {len(cases)} cases, step {done} of {steps}")
+        secs = time.perf_counter() - t0
+        bad = [i for i, s in enumerate(b.cases) if s.check() != lbm.IJ_OK]
+        b.close()
+        return secs, bad
+
+    t_raw, bad = run(raw)
+    t_fb, bad2 = run([stable[i] for i in bad]) if bad else (0.0, [])
+    return {"table": "256 nozzle cases, seed 1234, as written, 40000 steps each, diagnostics every 50",
+            "seconds": round(t_raw, 2), "unstable": len(bad), "fallback_seconds": round(t_fb, 2),
+            "fallback_unstable": len(bad2),
+            "cases_per_hour": round(len(raw) * 3600.0 / (t_raw + t_fb), 1),
+            "valid_cases_per_hour_without_fallback": round((len(raw) - len(bad)) * 3600.0 / t_raw, 1)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -328,6 +428,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep cases/hour measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional round-nozzle leg")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg of the sweep")
+    ap.add_argument("--extra", default="",
+                    help="comma list of legs not run by default: single_case (the 256x2048 case as written and "
+                         "scaled), sweep_as_written (the 256-case table unscaled, with fallbacks)")
     ap.add_argument("--kernel-steps", type=int, default=500,
                     help="launches timed back-to-back for the fused kernel's mean duration")
     ap.add_argument("--tiling", default="",
@@ -415,7 +519,7 @@ def main() -> int:
                    "nx": nx, "ny": ny, "diag_every": DIAG_EVERY, "tiling": args.tiling or "default"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_collide_fused (plain + general launch of one step)",
+                     "kernel": "k_collide_rows (plain rows) + k_collide_fused (rows next to walls), one step",
                      "kernel_ms": round(kern_ms, 5), "bytes_per_launch": BYTES_PER_NODE * fluid_nodes,
                      "traffic_gbs": None if traffic is None else round(traffic / (kern_ms * 1e-3) / 1e9, 1),
                      "copy_ceiling_gbs": round(copy_gbs, 1), "copy_ceiling_source": copy_src},
@@ -427,7 +531,13 @@ def main() -> int:
         out["round_nozzle_3d"] = round_nozzle_3d_bench(oracle=not args.no_cpu_baseline)
     if not args.no_sweep:
         out["sweep"] = sweep_bench()
-        out["sweep"]["surrogate"] = surrogate_bench()
+        if not args.no_surrogate:
+            out["sweep"]["surrogate"] = surrogate_bench()
+    extra = [e for e in args.extra.split(",") if e]
+    if "single_case" in extra:
+        out["single_case"] = single_case_bench()
+    if "sweep_as_written" in extra:
+        out["sweep_as_written"] = sweep_as_written_bench()
     if not args.no_cpu_baseline:
         log("cpu baseline: the FP64 oracle on a band of the droplet field")
         out["cpu_baseline"] = cpu_baseline(cfg)

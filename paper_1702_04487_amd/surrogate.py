@@ -12,8 +12,9 @@ t_neg, t_idle, drawn uniformly (sigma log-uniformly) from the sweep ranges.
 The solver runs the stable variant of each case (Gamma * sigma <= 0.01,
 pulse amplitudes scaled to a 0.2 viscous speed bound), a deterministic map
 of the inputs.  Targets (4): breakup step (the horizon when no drop
-detaches), drop velocity (0 without breakup), drop volume and the satellite
-flag.
+detaches), drop velocity (0 without breakup, and 0 for a breakup whose drop
+leaves no sample in the velocity window: such a case carries no velocity
+target), drop volume and the satellite flag.
 
 Command line (runs on the GPU):
     python -m paper_1702_04487_amd.surrogate generate --n 768 --seed 7 --out a.npz
@@ -215,32 +216,73 @@ class Surrogate:
         return mean, np.max(spread[:, :2] / self.y_std[:2], axis=1)
 
 
-def errors(pred: np.ndarray, y: np.ndarray, v_scale: float = 0.01):
-    """Relative errors of breakup step and drop velocity: |dt| / t and
-    |dv| / max(|v|, v_scale) (v_scale: a typical drop speed, so that cases
-    without a drop, v = 0, are scored on an absolute scale)."""
-    et = np.abs(pred[:, 0] - y[:, 0]) / np.maximum(np.abs(y[:, 0]), 1.0)
-    ev = np.abs(pred[:, 1] - y[:, 1]) / np.maximum(np.abs(y[:, 1]), v_scale)
-    return et, ev
+def scores(pred: np.ndarray, y: np.ndarray, horizon: float, v_scale: float = 0.01) -> dict:
+    """Per-case scores of predictions against solver targets.
+
+    - breakup / predicted: whether the case breaks up within the horizon
+      (targets) and whether the prediction says so (a predicted breakup step
+      below the horizon; predict() answers no breakup exactly);
+    - wrong: the two disagree;
+    - et: |dt_b| / t_b for cases that break up and are predicted to (NaN
+      elsewhere);
+    - ev: |dv| / max(|v|, v_scale) for those of them that have a drop
+      velocity (a stored v of exactly 0 marks a breakup whose drop left the
+      velocity window empty, diag v_drop NaN); NaN elsewhere."""
+    breakup = y[:, 0] < horizon
+    predicted = pred[:, 0] < horizon
+    both = breakup & predicted
+    has_v = breakup & (y[:, 1] != 0.0)
+    et = np.where(both, np.abs(pred[:, 0] - y[:, 0]) / np.maximum(np.abs(y[:, 0]), 1.0), np.nan)
+    ev = np.where(both & has_v, np.abs(pred[:, 1] - y[:, 1]) / np.maximum(np.abs(y[:, 1]), v_scale), np.nan)
+    return dict(breakup=breakup, predicted=predicted, wrong=breakup != predicted, et=et, ev=ev)
 
 
-def calibrate(spread: np.ndarray, et: np.ndarray, ev: np.ndarray, tol: float = 0.02, z: float = 1.645) -> float:
+def _bound_ok(values: np.ndarray, order: np.ndarray, tol: float, z: float) -> np.ndarray:
+    """For each prefix of `order` (the cases answered at a threshold), whether
+    the mean of the defined values plus z standard errors stays within tol
+    (true while no value is defined)."""
+    v = np.asarray(values, np.float64)[order]
+    d = np.isfinite(v)
+    k = np.cumsum(d)
+    s1 = np.cumsum(np.where(d, v, 0.0))
+    s2 = np.cumsum(np.where(d, v * v, 0.0))
+    kk = np.maximum(k, 1)
+    m = s1 / kk
+    var = np.maximum(s2 / kk - m * m, 0.0)
+    return (k == 0) | (m + z * np.sqrt(var / kk) <= tol)
+
+
+def calibrate(spread: np.ndarray, sc: dict, tol: float = 0.02, z: float = 1.645) -> float:
     """Largest spread threshold whose answered cases (spread <= threshold)
-    keep both mean errors within tol with one-sided confidence: the mean
-    plus z standard errors of the mean (z = 1.645: 95 %) must not exceed
-    tol (0 if no threshold qualifies).  The bound, rather than the sample
-    mean, keeps the choice of the largest qualifying threshold from
-    overfitting the calibration cases."""
+    keep, each with one-sided 95 % confidence (mean + z standard errors,
+    z = 1.645): the mean breakup-time error and the mean drop-velocity error
+    of the answered cases that break up within tol, and the rate of answered
+    cases whose breakup / no-breakup call is wrong within tol.  0 if no
+    threshold qualifies.  The bound, rather than the sample mean, keeps the
+    choice of the largest qualifying threshold from overfitting the
+    calibration cases."""
     order = np.argsort(spread)
-    k = np.arange(1, len(order) + 1)
-    ok = np.ones(len(order), bool)
-    for e in (et, ev):
-        e = np.asarray(e, np.float64)[order]
-        m = np.cumsum(e) / k
-        var = np.maximum(np.cumsum(e * e) / k - m * m, 0.0)
-        ok &= m + z * np.sqrt(var / k) <= tol
+    ok = _bound_ok(sc["et"], order, tol, z) & _bound_ok(sc["ev"], order, tol, z) & \
+        _bound_ok(sc["wrong"].astype(np.float64), order, tol, z)
     idx = np.nonzero(ok)[0]
     return float(spread[order][idx[-1]]) if len(idx) else 0.0
+
+
+def summary(sc: dict, answered: np.ndarray) -> dict:
+    """Held-out report: answered cases, their breakup / no-breakup accuracy,
+    and the breakup-time and drop-velocity errors (mean and 95th percentile)
+    over the answered cases that break up."""
+    a = answered
+    out = {"answered": int(a.sum()), "of": int(len(a)),
+           "class_accuracy": float(1.0 - sc["wrong"][a].mean()) if a.any() else None,
+           "answered_breakup": int((a & sc["breakup"]).sum())}
+    for key, name in (("et", "breakup_step"), ("ev", "v_drop")):
+        v = sc[key][a]
+        v = v[np.isfinite(v)]
+        out[f"err_{name}_mean"] = float(v.mean()) if len(v) else None
+        out[f"err_{name}_p95"] = float(np.percentile(v, 95)) if len(v) else None
+        out[f"err_{name}_n"] = int(len(v))
+    return out
 
 
 def main(argv: Optional[list] = None) -> int:

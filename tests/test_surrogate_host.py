@@ -44,23 +44,36 @@ def test_target_encoding():
     assert list(S.targets_of(lost, 24000)) == [16200.0, 0.0, 0.0, 0.0]
 
 
-def test_errors_and_calibration():
-    y = np.array([[10000.0, 0.02], [20000.0, 0.0], [5000.0, -0.01], [24000.0, 0.0]])
-    pred = np.array([[10100.0, 0.0202], [20000.0, 0.001], [6000.0, -0.01], [24000.0, 0.0]])
-    et, ev = S.errors(pred, y)
-    assert np.allclose(et, [0.01, 0.0, 0.2, 0.0])
-    assert np.allclose(ev, [0.01, 0.1, 0.0, 0.0])   # |v| < 0.01 measured against 0.01
-    spread = np.array([0.1, 0.3, 0.5, 0.05])
-    # ordered by spread: cases 3, 0, 1, 2; running means of e_t: 0, .005, .0033, .0525;
-    # of e_v: 0, .005, .0367 -> the last admissible prefix ends at case 0
-    # (the bound on the two-case prefix: .005 + 1.645 * .005 / sqrt 2 = .0108)
-    assert S.calibrate(spread, et, ev, tol=0.02) == 0.1
-    assert S.calibrate(spread, et + 1.0, ev, tol=0.02) == 0.0
+def test_scores_and_calibration():
+    H = 24000.0
+    # breakup (v defined), breakup whose drop left no velocity sample (v = 0),
+    # breakup, no breakup predicted as none, no breakup predicted as breakup
+    y = np.array([[10000.0, 0.02], [20000.0, 0.0], [5000.0, -0.01], [H, 0.0], [H, 0.0]])
+    pred = np.array([[10100.0, 0.0202], [20000.0, 0.001], [6000.0, -0.01], [H, 0.0], [23000.0, 0.003]])
+    sc = S.scores(pred, y, H)
+    assert list(sc["breakup"]) == [True, True, True, False, False]
+    assert list(sc["wrong"]) == [False, False, False, False, True]
+    assert np.allclose(sc["et"][:3], [0.01, 0.0, 0.2]) and np.isnan(sc["et"][3:]).all()
+    # v is scored only where the target has one: case 1 carries none
+    assert np.allclose(sc["ev"][[0, 2]], [0.01, 0.0]) and np.isnan(sc["ev"][[1, 3, 4]]).all()
+    spread = np.array([0.1, 0.3, 0.5, 0.05, 0.6])
+    # ordered by spread: cases 3, 0, 1, 2, 4.  Prefix ends and their bounds:
+    # case 3: nothing defined, no wrong call -> ok; case 0: et .01, ev .01 -> ok;
+    # case 1: et {.01, 0} (bound .005 + 1.645 * .005 / sqrt 2 = .0108) -> ok;
+    # case 2: et mean .07 -> refused; case 4: a wrong call -> refused
+    assert S.calibrate(spread, sc, tol=0.02) == 0.3
+    sc_bad = dict(sc, wrong=np.ones(5, bool))
+    assert S.calibrate(spread, sc_bad, tol=0.02) == 0.0
     # a prefix whose mean is within tol but whose bound is not is refused:
     # errors 0, .039 have mean .0195 and bound .0195 + 1.645 * .0195 / sqrt 2 = .042
-    s2, z2 = np.array([0.1, 0.2]), np.zeros(2)
-    assert S.calibrate(s2, np.array([0.0, 0.039]), z2, tol=0.02) == 0.1
-    assert S.calibrate(s2, np.array([0.0, 0.039]), z2, tol=0.02, z=0.0) == 0.2
+    s2 = np.array([0.1, 0.2])
+    sc2 = dict(et=np.array([0.0, 0.039]), ev=np.full(2, np.nan), wrong=np.zeros(2, bool))
+    assert S.calibrate(s2, sc2, tol=0.02) == 0.1
+    assert S.calibrate(s2, sc2, tol=0.02, z=0.0) == 0.2
+    rep = S.summary(sc, spread <= 0.3)
+    assert rep["answered"] == 3 and rep["class_accuracy"] == 1.0 and rep["answered_breakup"] == 2
+    assert rep["err_breakup_step_n"] == 2 and np.isclose(rep["err_breakup_step_mean"], 0.005)
+    assert rep["err_v_drop_n"] == 1 and np.isclose(rep["err_v_drop_mean"], 0.01)
 
 
 def test_predict_reads_breakup_near_horizon_as_none():
