@@ -138,13 +138,15 @@ def log(msg: str) -> None:
     print(f"bench.py: {msg}", file=sys.stderr, flush=True)
 
 
-def sweep_bench(batched_steps: int = 600, plain_steps: int = 300, plain_every: int = 16) -> dict:
+def sweep_bench(batched_steps: int = 600, plain_steps: int = 300, plain_every: int = 16, graph: int = 50) -> dict:
     """Cases per hour of the 256-case sweep table (seed 1234, the stable
     variant), 40000 steps per case, diagnostics every 50 steps: every case in
     one batch (autotuned tile shape, graphs of 50 steps) timed over
     `batched_steps` steps, against the same cases run one at a time through
     ij_step, each with its own autotuned tile shape (every `plain_every`-th
-    case timed over `plain_steps` steps)."""
+    case timed over `plain_steps` steps).  `graph` 0 launches the batch's
+    kernels one by one instead of replaying captured graphs (same kernels, for
+    per-dispatch counter collection)."""
     import torch
     import workloads as W
     from paper_1702_04487_amd import lbm
@@ -169,7 +171,8 @@ def sweep_bench(batched_steps: int = 600, plain_steps: int = 300, plain_every: i
     w, r, mixed, persistent, tune_ms = b.autotune(10)
     log(f"sweep: autotuned tile {w} waves x {r} rows, mixed strips {mixed}, persistent {persistent} "
         f"({tune_ms:.3f} ms per step)")
-    b.set_graph(50)
+    if graph:
+        b.set_graph(graph)
     b.step(100)
     ms_b = timed(lambda: b.step(batched_steps)) / batched_steps
     unstable = sum(1 for c in b.cases if c.check() != lbm.IJ_OK)
@@ -429,6 +432,8 @@ def main() -> int:
     ap.add_argument("--no-sweep", action="store_true", help="skip the sweep cases/hour measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the three-dimensional round-nozzle leg")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate leg of the sweep")
+    ap.add_argument("--sweep-graph", type=int, default=50,
+                    help="steps per captured graph of the batched sweep (0: plain launches)")
     ap.add_argument("--extra", default="",
                     help="comma list of legs not run by default: single_case (the 256x2048 case as written and "
                          "scaled), sweep_as_written (the 256-case table unscaled, with fallbacks)")
@@ -530,7 +535,7 @@ def main() -> int:
     if not args.no_3d:
         out["round_nozzle_3d"] = round_nozzle_3d_bench(oracle=not args.no_cpu_baseline)
     if not args.no_sweep:
-        out["sweep"] = sweep_bench()
+        out["sweep"] = sweep_bench(graph=args.sweep_graph)
         if not args.no_surrogate:
             out["sweep"]["surrogate"] = surrogate_bench()
     extra = [e for e in args.extra.split(",") if e]

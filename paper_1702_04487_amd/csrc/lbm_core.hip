@@ -1060,8 +1060,13 @@ __global__ __launch_bounds__(64 * NW) void k_collide_rows(KParams P, const float
                                                           const uint8_t* __restrict__ plain_rows, int n_strips,
                                                           int y_first, DiagRow* __restrict__ parts)
 {
-    const int y = y_first + (int)(blockIdx.x / (unsigned)n_strips);
-    const int strip = (int)(blockIdx.x - (unsigned)(y - y_first) * (unsigned)n_strips);
+    // XCD x (workgroup b % 8) takes the x-th contiguous run of the row-major
+    // (row, strip) numbering, so that the rows a wave reads g from (y - 1 and
+    // y + 1) are those its own XCD's L2 has just read or is about to read
+    const unsigned n = gridDim.x, b = blockIdx.x, xcd = b & 7u;
+    const unsigned tile = xcd * (n >> 3) + min(xcd, n & 7u) + (b >> 3);
+    const int y = y_first + (int)(tile / (unsigned)n_strips);
+    const int strip = (int)(tile - (unsigned)(y - y_first) * (unsigned)n_strips);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int x0 = (strip * NW + wave) * 64;   // first column of this wave's piece (uniform)
     if (y >= P.ny || x0 >= P.nx || !plain_rows[(size_t)strip * P.ny + y]) return;   // uniform over the wave
@@ -1512,16 +1517,19 @@ __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __rest
 }
 
 // The plain rows of every case of a batch without a walk: workgroup b takes
-// the row tile (case, row, first column of a strip of 64 NW columns) b of
-// the list, each wave 64 columns of it; waves past the case's last column
-// have nothing to do.  Tiles are listed case by case, row-major.
+// a row tile (case, row, first column of a strip of 64 NW columns) of the
+// list, each wave 64 columns of it; waves past the case's last column have
+// nothing to do.  Tiles are listed case by case, row-major, and XCD x
+// (workgroup b % 8) takes the x-th contiguous run of the list, so that
+// neighbouring rows of a case share one L2.
 template <int NW>
 __global__ __launch_bounds__(64 * NW) void k_batch_rows(const CaseRec* __restrict__ cases,
                                                         const int4* __restrict__ tiles, int parity,
                                                         const int64_t* __restrict__ t_dev,
                                                         const int* __restrict__ active)
 {
-    const int4 tl = tiles[blockIdx.x];   // (case, row, first column, 0)
+    const unsigned n = gridDim.x, b = blockIdx.x, xcd = b & 7u;
+    const int4 tl = tiles[xcd * (n >> 3) + min(xcd, n & 7u) + (b >> 3)];   // (case, row, first column, 0)
     if (!active[tl.x]) return;
     const CaseRec& R = cases[tl.x];
     const int x0 = tl.z + 64 * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
