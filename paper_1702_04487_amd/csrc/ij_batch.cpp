@@ -24,7 +24,7 @@ thread_local std::string g_batch_create_error;
 // whether the columns past the last full strip go to 64-column strips; each
 // with persistent workgroups and with one workgroup per tile
 const int kCandidates[][3] = {{1, 32, 0}, {2, 32, 0}, {2, 64, 0}, {4, 32, 0}, {4, 64, 0}, {2, 64, 1}, {4, 64, 1},
-                              {2, 1, 0},  {4, 1, 0}};
+                              {1, 1, 0},  {2, 1, 0},  {4, 1, 0}};
 
 // autotuned shapes by batch signature (lattice sizes, walls and diagnostics
 // interval of every case), for the life of the process

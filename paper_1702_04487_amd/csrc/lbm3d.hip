@@ -198,6 +198,13 @@ __device__ __forceinline__ Phi3 phi_fields(const K3& P, const double* __restrict
     return r;
 }
 
+// a load at a uniform base plus a 32-bit byte offset per lane (one address
+// register per lane instead of a 64-bit pair)
+__device__ __forceinline__ float ld_at(const float* __restrict__ base, unsigned bo)
+{
+    return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + bo);
+}
+
 // collide every fluid node and push its populations (Eqs. 3, 4, 8).
 // The workgroup first stages phi (sum g at fluid nodes, the ghost at solid
 // ones) and the wall bytes of its tile and a one-node halo (three y-slices)
@@ -205,6 +212,27 @@ __device__ __forceinline__ Phi3 phi_fields(const K3& P, const double* __restrict
 // issuing 36 scattered loads per node.
 constexpr int HX = BX + 2, HZ = BZ + 2, HN = 3 * HZ * HX;
 constexpr uint8_t kBeyond = 255;   // LDS wall byte of a node beyond an open row
+
+// a staging coordinate one step outside [0, n) wrapped back; coordinates
+// further out belong to no fluid node's stencil (the unused tail of a
+// partial tile) and are clamped in bounds
+__device__ __forceinline__ int wrap_stage(int a, int n)
+{
+    a = a < 0 ? a + n : (a >= n ? a - n : a);
+    return a < n ? a : n - 1;
+}
+
+// phi of a node from the populations of its lattice row (row base uniform)
+__device__ __forceinline__ double phi_of_row(const K3& P, const float* __restrict__ row,
+                                             const uint16_t* __restrict__ lo_row, int x)
+{
+    const unsigned xo = (unsigned)x << 2, pb = (unsigned)P.pitch << 2;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 1; i < QG; ++i) s += (double)ld_at(row, (unsigned)(Q + i) * pb + xo);
+    return (s + (double)bf16_to_float(lo_row[x])) + (double)ld_at(row, (unsigned)Q * pb + xo);
+}
+
 __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restrict__ A, float* __restrict__ B,
                                                      const uint8_t* __restrict__ wall,
                                                      const double* __restrict__ phi, float fb)
@@ -228,25 +256,43 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
     }
     const int x0 = bx * BX, z0 = bz * BZ;
     const int tid = threadIdx.y * BX + threadIdx.x;
-    for (int e = tid; e < HN; e += BX * BZ) {
-        const int dy = e / (HZ * HX), r = e - dy * (HZ * HX), ez = r / HX, ex = r - ez * HX;
-        const int xx = ((x0 - 1 + ex) % P.nx + P.nx) % P.nx, zz = ((z0 - 1 + ez) % P.nz + P.nz) % P.nz;
+    const size_t rlen = (size_t)NPL * P.pitch;   // floats of one lattice row's 26 populations
+    const uint16_t* loA = lo3(P, A);
+    // one halo row (slice dy, z-row ez) at staging columns ex (x = x0 - 1 + ex)
+    auto stage = [&](int hr, int ex) {
+        const int dy = hr / HZ, ez = hr - dy * HZ;
         const int yy = y - 1 + dy;
+        const int zz = wrap_stage(z0 - 1 + ez, P.nz);
+        const int xx = wrap_stage(x0 - 1 + ex, P.nx);
         const bool beyond = (yy < 0 || yy >= P.ny) && P.bc_open;
-        const size_t ks = nodek(P, xx, stencil_row(P, yy), zz);
-        s_phi[e] = wall[ks] ? phi[ks] : phi_of_g(P, A, ks, xx);
-        s_w[e] = beyond ? kBeyond : wall[nodek(P, xx, wrapi(yy, P.ny), zz)];
+        const size_t rs = (size_t)((unsigned)stencil_row(P, yy) * (unsigned)P.nz + (unsigned)zz);
+        const uint8_t* ws = wall + rs * P.pitch;
+        const double* ps = phi + rs * P.pitch;
+        const int e = hr * HX + ex;
+        s_phi[e] = ws[xx] ? ps[xx] : phi_of_row(P, A + rs * rlen, loA + rs * P.pitch, xx);
+        s_w[e] = beyond ? kBeyond
+                        : wall[(size_t)((unsigned)wrapi(yy, P.ny) * (unsigned)P.nz + (unsigned)zz) * P.pitch + xx];
+    };
+    for (int e = tid; e < HN; e += BX * BZ) {
+        const int hr = e / HX;
+        stage(hr, e - hr * HX);
     }
     __syncthreads();
-    const int x = x0 + threadIdx.x, z = z0 + threadIdx.y;
-    const int lc = (HZ + threadIdx.y + 1) * HX + threadIdx.x + 1;   // LDS index of this node (middle slice)
+    // a wave's 64 lanes lie along x at one z: the node's lattice row, and
+    // with it every row address below, is uniform over the wave
+    const int zl = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const int x = x0 + threadIdx.x, z = z0 + zl;
+    const int lc = (HZ + zl + 1) * HX + threadIdx.x + 1;   // LDS index of this node (middle slice)
     if (x >= P.nx || z >= P.nz || s_w[lc]) return;
     const size_t k = nodek(P, x, y, z);
+    const size_t r0 = (size_t)((unsigned)y * (unsigned)P.nz + (unsigned)z);
+    const float* Ar = A + r0 * rlen;
+    const unsigned pb = (unsigned)P.pitch << 2, xo = (unsigned)x << 2;   // byte offsets within the row
     float f[Q], g[QG];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = A[pidx(P, k, x, i)];
+    for (int i = 0; i < Q; ++i) f[i] = ld_at(Ar, (unsigned)i * pb + xo);
 #pragma unroll
-    for (int i = 0; i < QG; ++i) g[i] = A[pidx(P, k, x, Q + i)];
+    for (int i = 0; i < QG; ++i) g[i] = ld_at(Ar, (unsigned)(Q + i) * pb + xo);
 
     auto lds = [&](int i) { return lc + CY[i] * (HZ * HX) + CZ[i] * HX + CX[i]; };
     Phi3 ph;
