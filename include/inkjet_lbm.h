@@ -143,6 +143,13 @@ ij_status ij_attach_buffers(ij_sim *s, void *pdf_a, void *pdf_b, size_t bytes_ea
  * have fluid directly above (below) it.  Invalidates the state. */
 ij_status ij_set_wall(ij_sim *s, const uint8_t *wall_host);
 
+/* ij_set_wall from a mask on the host (on_device = 0) or on the device
+ * (on_device != 0: device array of ny*nx bytes, copied to the host for the
+ * wall analysis; synchronises the device).  Same classes, checks and
+ * effect as ij_set_wall (geometry of the nozzle: "Reproducing the
+ * experiment", wall classes of the two contact angles). */
+ij_status ij_set_solid_mask(ij_sim *s, const uint8_t *mask, int32_t on_device);
+
 /* Initial state from a signed distance d (device, [ny][nx], positive inside
  * the ink): phi = phi* tanh(2 d / W), n = n0, u = 0, f = f_eq, g = g_eq
  * (Eqs. 5-6, 9-10) with mu from this phi including the wetting ghosts.
@@ -341,6 +348,14 @@ typedef struct ij_mlp ij_mlp;
 
 /* n_members (1..64) members with zero parameters and unit scaling. */
 ij_status ij_mlp_create(int32_t n_members, ij_mlp **out);
+
+/* n_members members with seeded initial parameters: parameter j (packed
+ * layout below) of member k is -a + 2a u_j, a = 1/sqrt(fan_in of its
+ * layer) (7, 128, 128), u_j = (x_j >> 11) / 2^53 with x_j output j + 1 of
+ * SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) started at seed + 1000 k;
+ * stored as float like ij_mlp_set_weights.  Unit scaling, Adam moments
+ * zero.  Synchronises the device; *out is NULL on failure. */
+ij_status ij_mlp_create_seeded(int32_t n_members, uint64_t seed, ij_mlp **out);
 void ij_mlp_destroy(ij_mlp *m);
 const char *ij_mlp_last_error(const ij_mlp *m);
 int32_t ij_mlp_param_count(void);

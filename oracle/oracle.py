@@ -23,14 +23,24 @@ SRC = os.path.join(HERE, "lbm_oracle.c")
 LIB = os.path.join(HERE, "liblbm_oracle.so")
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (OpenMP, strict IEEE double arithmetic)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp",
+# Flags of the sanitizer build (AddressSanitizer and UndefinedBehaviorSanitizer)
+SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
+
+
+def build(force: bool = True, out: Optional[str] = None, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (OpenMP, strict IEEE double arithmetic).
+
+    With `sanitize`: the same source built with SANITIZE instead of -O2
+    into `out`, the library that the test-suite's sanitizer run loads
+    through the IJ_ORACLE_LIB environment variable."""
+    target = out or LIB
+    if sanitize or force or not os.path.exists(target) or os.path.getmtime(target) < os.path.getmtime(SRC):
+        tmp = target + ".tmp"
+        opt = SANITIZE if sanitize else ["-O2"]
+        subprocess.check_call(["gcc", *opt, "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp",
                                "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, target)
+    return target
 
 
 class _Params(ctypes.Structure):
@@ -49,9 +59,10 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        path = os.environ.get("IJ_ORACLE_LIB") or LIB
+        if path == LIB and not os.path.exists(LIB):
             build()
-        L = ctypes.CDLL(LIB)
+        L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         L.o_create.restype = ctypes.c_void_p
         L.o_create.argtypes = [ctypes.POINTER(_Params), ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]

@@ -1,9 +1,12 @@
-"""Build the HIP library (``libinkjet_lbm.so``) and the copy calibration
-program (``bin/copy_calib``) in-tree for gfx950."""
+"""Build the HIP library (``libinkjet_lbm.so``), the copy calibration
+program (``bin/copy_calib``) and the C ABI exercise with its host code under
+AddressSanitizer and UndefinedBehaviorSanitizer (``bin/abi_exercise_asan``,
+run by the test-suite) in-tree for gfx950."""
 from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -12,6 +15,12 @@ LIB = os.path.join(HERE, "libinkjet_lbm.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("lbm_core.hip", "ij_api.cpp", "ij_batch.cpp", "mlp.hip", "ij_mlp.cpp",
                                           "lbm3d.hip")]
 CALIB = os.path.join(HERE, "bin", "copy_calib")
+EXERCISE_SRC = os.path.join(ROOT, "tests", "native", "abi_exercise.cpp")
+EXERCISE = os.path.join(HERE, "bin", "abi_exercise_asan")
+CLANGXX = os.environ.get("CLANGXX", "/opt/rocm/llvm/bin/clang++")
+# host code only: the device code of these objects is built as usual
+SANITIZE_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                 "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # -packed-fp32-ops: no v_pk_*_f32 (their forms are avoided on this target);
@@ -35,6 +44,28 @@ def _hipcc(args, verbose):
         print(msg)
 
 
+def build_exercise(verbose: bool = False) -> str:
+    """The library sources and tests/native/abi_exercise.cpp compiled with
+    SANITIZE_HOST (one object each, in parallel), linked by clang++ with the
+    sanitizer runtimes."""
+    obj_dir = os.path.join(HERE, "bin", "abi_exercise_objs")
+    os.makedirs(obj_dir, exist_ok=True)
+    srcs = SOURCES + [EXERCISE_SRC]
+    objs = [os.path.join(obj_dir, os.path.basename(f) + ".o") for f in srcs]
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        jobs = [ex.submit(_hipcc, [*SANITIZE_HOST, "-c", "-x", "hip", src, "-o", obj], verbose)
+                for src, obj in zip(srcs, objs)]
+        for j in jobs:
+            j.result()
+    link = [CLANGXX, "-fsanitize=address,undefined", "-o", EXERCISE + ".tmp", *objs,
+            "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"]
+    r = subprocess.run(link, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link of the sanitizer exercise failed:\n" + r.stdout + r.stderr)
+    os.replace(EXERCISE + ".tmp", EXERCISE)
+    return EXERCISE
+
+
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     _hipcc(["-shared", "-o", tmp, *SOURCES], verbose)
@@ -42,6 +73,7 @@ def build(verbose: bool = False) -> str:
     os.makedirs(os.path.dirname(CALIB), exist_ok=True)
     _hipcc(["-o", CALIB + ".tmp", os.path.join(CSRC, "copy_calib.hip")], verbose)
     os.replace(CALIB + ".tmp", CALIB)
+    build_exercise(verbose)
     return LIB
 
 

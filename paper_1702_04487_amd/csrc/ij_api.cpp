@@ -514,6 +514,18 @@ ij_status ij_set_wall(ij_sim* s, const uint8_t* w)
     return upload_wall(s);
 }
 
+ij_status ij_set_solid_mask(ij_sim* s, const uint8_t* mask, int32_t on_device)
+{
+    if (!s) return IJ_ERR_INVALID_ARG;
+    if (!mask) return fail(s, IJ_ERR_INVALID_ARG, "mask is NULL");
+    if (!on_device) return ij_set_wall(s, mask);
+    // the host analysis (wall classes, ghost and tile lists) reads a host copy
+    std::vector<uint8_t> h((size_t)s->nx * s->ny);
+    const hipError_t e = hipMemcpy(h.data(), mask, h.size(), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(s, e, "copy of the device mask");
+    return ij_set_wall(s, h.data());
+}
+
 static ij_status do_init(ij_sim* s, const float* src, int from_distance, const float* ux, const float* uy,
                          void* stream)
 {

@@ -133,6 +133,42 @@ const char* ij_mlp_last_error(const ij_mlp* m) { return m ? m->err.c_str() : g_m
 
 int32_t ij_mlp_param_count(void) { return kMlpPacked; }
 
+ij_status ij_mlp_create_seeded(int32_t n_members, uint64_t seed, ij_mlp** out)
+{
+    ij_status r = ij_mlp_create(n_members, out);
+    if (r != IJ_OK) return r;
+    // member k: draw j of SplitMix64 (Steele, Lea & Flood 2014) started at
+    // seed + 1000 k gives packed parameter j, uniform in +-1/sqrt(fan_in)
+    // of its layer (u = top 53 bits / 2^53)
+    std::vector<double> packed(kMlpParams);
+    const int fan_in[3] = {kMlpIn, kMlpHidden, kMlpHidden};
+    const int fan_out[3] = {kMlpHidden, kMlpHidden, kMlpOut};
+    for (int k = 0; k < n_members; ++k) {
+        const uint64_t s0 = seed + 1000ull * (uint64_t)k;
+        size_t j = 0;
+        for (int l = 0; l < 3; ++l) {
+            const double a = 1.0 / std::sqrt((double)fan_in[l]);
+            const size_t count = (size_t)fan_out[l] * fan_in[l] + fan_out[l];   // W then b
+            for (size_t c = 0; c < count; ++c, ++j) {
+                uint64_t z = s0 + (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull;
+                z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+                z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+                z ^= z >> 31;
+                const double u = (double)(z >> 11) * (1.0 / 9007199254740992.0);
+                const double span = (a - -a) * u;   // two statements: no fused multiply-add
+                packed[j] = -a + span;
+            }
+        }
+        r = ij_mlp_set_weights(*out, k, packed.data());
+        if (r != IJ_OK) {
+            ij_mlp_destroy(*out);
+            *out = nullptr;
+            return r;
+        }
+    }
+    return IJ_OK;
+}
+
 ij_status ij_mlp_set_weights(ij_mlp* m, int32_t member, const double* packed)
 {
     if (!m || !packed) return IJ_ERR_INVALID_ARG;

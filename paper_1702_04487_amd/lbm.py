@@ -55,7 +55,7 @@ _lib = None
 
 # every symbol the header declares (checked by the CPU test-suite)
 EXPORTS = ["ij_params_default", "ij_create", "ij_destroy", "ij_last_error", "ij_required_bytes",
-           "ij_attach_buffers", "ij_set_wall", "ij_init_distance", "ij_init_phi", "ij_init_default",
+           "ij_attach_buffers", "ij_set_wall", "ij_set_solid_mask", "ij_init_distance", "ij_init_phi", "ij_init_default",
            "ij_step", "ij_step_reference", "ij_time", "ij_get_moments", "ij_get_state", "ij_set_state",
            "ij_state_bytes", "ij_save_state", "ij_load_state",
            "ij_diag_sample", "ij_get_row_profile", "ij_get_samples", "ij_get_diagnostics", "ij_check",
@@ -63,7 +63,7 @@ EXPORTS = ["ij_params_default", "ij_create", "ij_destroy", "ij_last_error", "ij_
            "ij_batch_create", "ij_batch_destroy", "ij_batch_last_error", "ij_batch_size", "ij_batch_case",
            "ij_batch_time", "ij_batch_step", "ij_batch_set_graph", "ij_batch_set_tiling", "ij_batch_get_tiling",
            "ij_batch_autotune",
-           "ij_mlp_create", "ij_mlp_destroy", "ij_mlp_last_error", "ij_mlp_param_count", "ij_mlp_set_weights",
+           "ij_mlp_create", "ij_mlp_create_seeded", "ij_mlp_destroy", "ij_mlp_last_error", "ij_mlp_param_count", "ij_mlp_set_weights",
            "ij_mlp_get_weights", "ij_mlp_set_scaling", "ij_mlp_gradients", "ij_mlp_train", "ij_mlp_predict",
            "ij_mlp_predict_noalloc",
            "ij3_create", "ij3_destroy", "ij3_last_error", "ij3_init", "ij3_step", "ij3_time", "ij3_get_moments",
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
         "ij_required_bytes": (st, [ctypes.POINTER(IJParams), ctypes.POINTER(ctypes.c_size_t)]),
         "ij_attach_buffers": (st, [vp, vp, vp, ctypes.c_size_t]),
         "ij_set_wall": (st, [vp, vp]),
+        "ij_set_solid_mask": (st, [vp, vp, i32]),
         "ij_init_distance": (st, [vp, vp, vp]),
         "ij_init_phi": (st, [vp, vp, vp, vp, vp]),
         "ij_init_default": (st, [vp, vp]),
@@ -140,6 +141,7 @@ def load(path: str = LIB_PATH):
         "ij_batch_autotune": (st, [vp, i32, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                                    ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)]),
         "ij_mlp_create": (st, [i32, ctypes.POINTER(vp)]),
+        "ij_mlp_create_seeded": (st, [i32, ctypes.c_uint64, ctypes.POINTER(vp)]),
         "ij_mlp_destroy": (None, [vp]),
         "ij_mlp_last_error": (ctypes.c_char_p, [vp]),
         "ij_mlp_param_count": (i32, []),
@@ -240,7 +242,16 @@ class Sim:
             pass
 
     # ------------------------------------------------------------ set-up
-    def set_wall(self, wall: np.ndarray):
+    def set_wall(self, wall):
+        """Wall mask [ny, nx] of IJ_FLUID / IJ_WALL_INNER / IJ_WALL_OUTER: a
+        host array (:c:func:`ij_set_wall`) or a uint8 tensor on the device
+        (:c:func:`ij_set_solid_mask` with on_device = 1)."""
+        if hasattr(wall, "is_cuda") and wall.is_cuda:
+            import torch
+            assert wall.dtype == torch.uint8 and tuple(wall.shape) == (self.ny, self.nx)
+            w = wall.contiguous()
+            self._check(self.L.ij_set_solid_mask(self.h, ctypes.c_void_p(w.data_ptr()), 1))
+            return
         w = np.ascontiguousarray(wall, dtype=np.uint8)
         assert w.shape == (self.ny, self.nx)
         self._check(self.L.ij_set_wall(self.h, w.ctypes.data_as(ctypes.c_void_p)))
@@ -469,11 +480,16 @@ def unpack_params(v: np.ndarray) -> dict:
 class MLP:
     """Ensemble of surrogate networks (:c:func:`ij_mlp_create`)."""
 
-    def __init__(self, n_members: int = 4):
+    def __init__(self, n_members: int = 4, seed: Optional[int] = None):
+        """Zero parameters, or with `seed` the seeded initial parameters of
+        :c:func:`ij_mlp_create_seeded`."""
         import torch
         self.L = load()
         h = ctypes.c_void_p()
-        r = self.L.ij_mlp_create(int(n_members), ctypes.byref(h))
+        if seed is None:
+            r = self.L.ij_mlp_create(int(n_members), ctypes.byref(h))
+        else:
+            r = self.L.ij_mlp_create_seeded(int(n_members), ctypes.c_uint64(int(seed) & (2 ** 64 - 1)), ctypes.byref(h))
         if r != IJ_OK:
             raise LBMError(r, self.L.ij_mlp_last_error(None).decode())
         self.h = h

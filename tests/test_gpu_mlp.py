@@ -113,3 +113,17 @@ def test_training_follows_oracle(gpu_lib):
         assert rel(o_gpu[:, :3], o_ref[:, :3] * Y_STD + Y_MEAN) < 0.1
         assert np.isfinite(pack := np.concatenate([w[nm].ravel() for nm in M.NAMES])).all()
     net.close()
+
+
+def test_seeded_create_draws_the_published_generator(gpu_lib):
+    """ij_mlp_create_seeded: member k holds, as float, the uniform draws of
+    SplitMix64 started at seed + 1000 k (workloads.mlp_init, written from
+    the generator's definition in Python), bit for bit."""
+    seed = 4242
+    net = gpu_lib.MLP(3, seed=seed)
+    for k in range(3):
+        got = net.get_weights(k)
+        ref = W.mlp_init(seed + 1000 * k)
+        for name in ("W1", "b1", "W2", "b2", "W3", "b3"):
+            assert np.array_equal(np.asarray(got[name]), ref[name].astype(np.float32).astype(np.float64)), (k, name)
+    net.close()

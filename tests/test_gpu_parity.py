@@ -365,6 +365,30 @@ def test_attached_caller_buffers(gpu_lib):
     assert np.array_equal(_np(a.state()[0]), _np(b.state()[0]))
 
 
+def test_solid_mask_from_the_device(gpu_lib):
+    """ij_set_solid_mask with a device mask sets the same walls as
+    ij_set_wall with the host copy: the two runs are bit for bit equal, and
+    a mask with a bad wall class is refused from either side."""
+    import torch
+    c = _case("walls_block")
+    p, wall, d = c
+    a = gpu_lib.Sim(p, np.zeros_like(wall))
+    a.set_wall(torch.from_numpy(np.ascontiguousarray(wall)).cuda())
+    a.init_distance(d)
+    a.step(40)
+    b = gpu_lib.Sim(p, np.zeros_like(wall))
+    b.set_wall(wall)
+    b.init_distance(d)
+    b.step(40)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(_bits(x), _bits(y))
+    bad = wall.copy()
+    bad[3, 3] = 7
+    with pytest.raises(gpu_lib.LBMError) as e:
+        a.set_wall(torch.from_numpy(bad).cuda())
+    assert e.value.code == gpu_lib.IJ_ERR_INVALID_ARG
+
+
 # --------------------------------------------------- full-size sampling
 def test_full_size_droplet_field_sampled(oracle_mod, gpu_lib):
     """2048 x 16384 disc field at full size with the default tiling: windows
