@@ -11,9 +11,12 @@
 //   W1 [128][16]  (inputs 7..15 zero)   b1 [128]
 //   W2 [128][128]                         b2 [128]
 //   W3 [16][128]  (outputs 4..15 zero)   b3 [16]
-// One matrix-core product is v_mfma_f32_16x16x16_bf16: D[16x16] += A[16x16]
-// B[16x16]; lane l holds A[l % 16][4 (l / 16) + q], B[4 (l / 16) + q][l % 16]
-// and D[4 (l / 16) + q][l % 16] for q = 0..3.
+// Matrix-core products: v_mfma_f32_16x16x32_bf16 (gfx950), D[16x16] +=
+// A[16x32] B[32x16], with lane l holding A[l % 16][8 (l / 16) + j] and
+// B[8 (l / 16) + j][l % 16] for j = 0..7; where the inner dimension leaves 16
+// (the first layer's 16 padded inputs, minibatches of an odd number of 16-row
+// tiles) v_mfma_f32_16x16x16_bf16, with A[l % 16][4 (l / 16) + q] and
+// B[4 (l / 16) + q][l % 16].  Both give D[4 (l / 16) + q][l % 16], q = 0..3.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,6 +27,7 @@
 namespace ij {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 namespace {
@@ -54,8 +58,19 @@ __device__ __forceinline__ f32x4 mma16(const uint16_t* A, int ars, int acs, cons
                                        int r0, int c0, int K, f32x4 acc)
 {
     const int lane = threadIdx.x & 63;
-    const int i = lane & 15, kq = 4 * (lane >> 4);
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    const int i = lane & 15;
+    int k0 = 0;
+    for (const int k8 = 8 * (lane >> 4); k0 + 32 <= K; k0 += 32) {
+        bf16x8 a, b;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            a[j] = __builtin_bit_cast(__bf16, A[(size_t)(r0 + i) * ars + (size_t)(k0 + k8 + j) * acs]);
+            b[j] = __builtin_bit_cast(__bf16, B[(size_t)(k0 + k8 + j) * brs + (size_t)(c0 + i) * bcs]);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    }
+    if (k0 < K) {   // the last 16 of the inner dimension
+        const int kq = 4 * (lane >> 4);
         bf16x4 a, b;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -319,8 +334,10 @@ __global__ void k_mlp_refresh(MlpDev D)
 
 // ---------------------------------------------------------------- inference
 //
-// four consecutive bfloat16 values (8-byte aligned) as one fragment register
+// four (eight) consecutive bfloat16 values, 8-byte (16-byte) aligned, as one
+// fragment of the 16x16x16 (16x16x32) product
 __device__ __forceinline__ bf16x4 frag4(const uint16_t* p) { return *reinterpret_cast<const bf16x4*>(p); }
+__device__ __forceinline__ bf16x8 frag8(const uint16_t* p) { return *reinterpret_cast<const bf16x8*>(p); }
 
 // grid (query blocks of kInferRows * MT / 64, member): each wave evaluates
 // kInferRows queries (two row tiles) through the three layers with bfloat16
@@ -337,7 +354,7 @@ __global__ __launch_bounds__(MT) void k_mlp_infer(MlpDev D, MlpNorm N, const flo
     const int mem = blockIdx.y;
     const Member P = member(D, mem);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = lane & 15, kq = 4 * (lane >> 4);
+    const int i = lane & 15, kq = 4 * (lane >> 4), k8 = 8 * (lane >> 4);
     const int q0 = (blockIdx.x * (MT / 64) + wave) * kInferRows;
     __shared__ __align__(16) uint16_t s_x[MT / 64][kInferRows * 16];
     __shared__ __align__(16) uint16_t s_a[MT / 64][2][kInferRows * 128];
@@ -372,12 +389,12 @@ __global__ __launch_bounds__(MT) void k_mlp_infer(MlpDev D, MlpNorm N, const flo
         f32x4 acc[kInferTiles];
 #pragma unroll
         for (int rt = 0; rt < kInferTiles; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < 128; k0 += 16) {
-            const bf16x4 b = frag4(W2 + (nt * 16 + i) * 128 + k0 + kq);
+        for (int k0 = 0; k0 < 128; k0 += 32) {
+            const bf16x8 b = frag8(W2 + (nt * 16 + i) * 128 + k0 + k8);
 #pragma unroll
             for (int rt = 0; rt < kInferTiles; ++rt)
-                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag4(a1 + (rt * 16 + i) * 128 + k0 + kq), b,
-                                                                    acc[rt], 0, 0, 0);
+                acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag8(a1 + (rt * 16 + i) * 128 + k0 + k8), b,
+                                                                 acc[rt], 0, 0, 0);
         }
         const int c = nt * 16 + tile_col();
         const float bias = P.w[kMlpB2 + c];
@@ -391,12 +408,12 @@ __global__ __launch_bounds__(MT) void k_mlp_infer(MlpDev D, MlpNorm N, const flo
     f32x4 acc[kInferTiles];
 #pragma unroll
     for (int rt = 0; rt < kInferTiles; ++rt) acc[rt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < 128; k0 += 16) {
-        const bf16x4 b = frag4(W3 + i * 128 + k0 + kq);
+    for (int k0 = 0; k0 < 128; k0 += 32) {
+        const bf16x8 b = frag8(W3 + i * 128 + k0 + k8);
 #pragma unroll
         for (int rt = 0; rt < kInferTiles; ++rt)
-            acc[rt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(frag4(a2 + (rt * 16 + i) * 128 + k0 + kq), b, acc[rt],
-                                                                0, 0, 0);
+            acc[rt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag8(a2 + (rt * 16 + i) * 128 + k0 + k8), b, acc[rt],
+                                                             0, 0, 0);
     }
     const int c = tile_col();
     if (c < kMlpOut) {
