@@ -222,17 +222,6 @@ __device__ __forceinline__ int wrap_stage(int a, int n)
     return a < n ? a : n - 1;
 }
 
-// phi of a node from the populations of its lattice row (row base uniform)
-__device__ __forceinline__ double phi_of_row(const K3& P, const float* __restrict__ row,
-                                             const uint16_t* __restrict__ lo_row, int x)
-{
-    const unsigned xo = (unsigned)x << 2, pb = (unsigned)P.pitch << 2;
-    double s = 0.0;
-#pragma unroll
-    for (int i = 1; i < QG; ++i) s += (double)ld_at(row, (unsigned)(Q + i) * pb + xo);
-    return (s + (double)bf16_to_float(lo_row[x])) + (double)ld_at(row, (unsigned)Q * pb + xo);
-}
-
 __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restrict__ A, float* __restrict__ B,
                                                      const uint8_t* __restrict__ wall,
                                                      const double* __restrict__ phi, float fb)
@@ -258,24 +247,60 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
     const int tid = threadIdx.y * BX + threadIdx.x;
     const size_t rlen = (size_t)NPL * P.pitch;   // floats of one lattice row's 26 populations
     const uint16_t* loA = lo3(P, A);
-    // one halo row (slice dy, z-row ez) at staging columns ex (x = x0 - 1 + ex)
-    auto stage = [&](int hr, int ex) {
+    // the halo tile: entry e = (slice dy, z-row ez, column ex), x = x0 - 1 + ex.
+    // Each thread takes entries tid, tid + 512, ...: first the coordinates
+    // and wall bytes of all of them, then the loads of all of them (the g
+    // rows of a fluid entry, the ghost phi of a solid one), then the sums,
+    // so that the loads of its entries are in flight together
+    constexpr int NS = (HN + BX * BZ - 1) / (BX * BZ);
+    size_t rsk[NS];
+    int xk[NS];
+    uint8_t wk[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int e = tid + k * BX * BZ;
+        if (e >= HN) break;
+        const int hr = e / HX, ex = e - hr * HX;
         const int dy = hr / HZ, ez = hr - dy * HZ;
         const int yy = y - 1 + dy;
         const int zz = wrap_stage(z0 - 1 + ez, P.nz);
         const int xx = wrap_stage(x0 - 1 + ex, P.nx);
         const bool beyond = (yy < 0 || yy >= P.ny) && P.bc_open;
-        const size_t rs = (size_t)((unsigned)stencil_row(P, yy) * (unsigned)P.nz + (unsigned)zz);
-        const uint8_t* ws = wall + rs * P.pitch;
-        const double* ps = phi + rs * P.pitch;
-        const int e = hr * HX + ex;
-        s_phi[e] = ws[xx] ? ps[xx] : phi_of_row(P, A + rs * rlen, loA + rs * P.pitch, xx);
+        rsk[k] = (size_t)((unsigned)stencil_row(P, yy) * (unsigned)P.nz + (unsigned)zz);
+        xk[k] = xx;
+        wk[k] = wall[rsk[k] * P.pitch + xx];
         s_w[e] = beyond ? kBeyond
                         : wall[(size_t)((unsigned)wrapi(yy, P.ny) * (unsigned)P.nz + (unsigned)zz) * P.pitch + xx];
-    };
-    for (int e = tid; e < HN; e += BX * BZ) {
-        const int hr = e / HX;
-        stage(hr, e - hr * HX);
+    }
+    float gk[NS][QG];
+    uint16_t lk[NS];
+    double pk[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        if (tid + k * BX * BZ >= HN) break;
+        if (wk[k]) {
+            pk[k] = phi[rsk[k] * P.pitch + xk[k]];
+        } else {
+            const float* row = A + rsk[k] * rlen;
+            const unsigned xo = (unsigned)xk[k] << 2, pb = (unsigned)P.pitch << 2;
+#pragma unroll
+            for (int i = 0; i < QG; ++i) gk[k][i] = ld_at(row, (unsigned)(Q + i) * pb + xo);
+            lk[k] = loA[rsk[k] * P.pitch + xk[k]];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        const int e = tid + k * BX * BZ;
+        if (e >= HN) break;
+        if (wk[k]) {
+            s_phi[e] = pk[k];
+        } else {
+            // the order of phi_of_g: g_1 .. g_6, the remainder, then g_0
+            double sum = 0.0;
+#pragma unroll
+            for (int i = 1; i < QG; ++i) sum += (double)gk[k][i];
+            s_phi[e] = (sum + (double)bf16_to_float(lk[k])) + (double)gk[k][0];
+        }
     }
     __syncthreads();
     // a wave's 64 lanes lie along x at one z: the node's lattice row, and
