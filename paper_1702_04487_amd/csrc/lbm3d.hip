@@ -222,7 +222,10 @@ __device__ __forceinline__ int wrap_stage(int a, int n)
     return a < n ? a : n - 1;
 }
 
-__global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restrict__ A, float* __restrict__ B,
+// (six waves per SIMD, three workgroups per CU: the register budget this asks
+// for keeps the destinations' old g loaded early at the cost of a few spilled
+// registers, measured faster than five waves without spills)
+__global__ __launch_bounds__(BX* BZ) __attribute__((amdgpu_waves_per_eu(6))) void k3_collide(K3 P, const float* __restrict__ A, float* __restrict__ B,
                                                      const uint8_t* __restrict__ wall,
                                                      const double* __restrict__ phi, float fb)
 {
@@ -318,6 +321,15 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
     for (int i = 0; i < Q; ++i) f[i] = ld_at(Ar, (unsigned)i * pb + xo);
 #pragma unroll
     for (int i = 0; i < QG; ++i) g[i] = ld_at(Ar, (unsigned)(Q + i) * pb + xo);
+    // the old g_i at each destination (Eq. 8 keeps (1-q) of it), loaded with
+    // the node's own populations; every address is in the lattice (a solid
+    // destination or one beyond an open row is loaded and not used)
+    float gd[QG];
+#pragma unroll
+    for (int i = 1; i < QG; ++i) {
+        const int xd = wrapi(x + CX[i], P.nx);
+        gd[i] = A[pidx(P, nodek(P, xd, wrapi(y + CY[i], P.ny), wrapi(z + CZ[i], P.nz)), xd, Q + i)];
+    }
 
     auto lds = [&](int i) { return lc + CY[i] * (HZ * HX) + CZ[i] * HX + CX[i]; };
     Phi3 ph;
@@ -427,7 +439,7 @@ __global__ __launch_bounds__(BX* BZ) void k3_collide(K3 P, const float* __restri
         } else {
             const int xd = wrapi(x + CX[i], P.nx);
             const size_t pd = pidx(P, nodek(P, xd, wrapi(y + CY[i], P.ny), wrapi(z + CZ[i], P.nz)), xd, Q + i);
-            B[pd] = h + P.omq * A[pd];
+            B[pd] = h + P.omq * gd[i];
         }
     }
 }
