@@ -253,7 +253,7 @@ ij_status stage(ij_batch* b, hipStream_t st)
     IJB_HIP(b, hipMemcpyAsync(b->d_nrec, b->h_nrec, n * sizeof(int64_t), hipMemcpyHostToDevice, st));
     IJB_HIP(b, hipMemcpyAsync(b->d_active, b->h_active, n * sizeof(int), hipMemcpyHostToDevice, st));
     IJB_HIP(b, hipEventRecord(b->staged, st));
-    IJB_HIP(b, ij::launch_batch_set_time(b->d_t, b->t, st));
+    IJB_HIP(b, ij::launch_batch_set_time(b->d_t, b->t, b->d_cases, (int)b->sims.size(), st));
     return IJ_OK;
 }
 
@@ -266,7 +266,7 @@ hipError_t one_step(ij_batch* b, int parity, bool diag, bool with_tick, hipStrea
         e = ij::launch_batch_diag(b->d_cases, (int)b->sims.size(), b->max_nx, b->max_ny, b->max_ghost, parity, b->d_t,
                                   b->d_nrec, b->d_active, st);
     if (e == hipSuccess)
-        e = ij::launch_batch_collide(b->T, b->d_cases, parity, b->d_t, b->d_active, b->waves_x, st);
+        e = ij::launch_batch_collide(b->T, b->d_cases, parity, b->d_active, b->waves_x, st);
     if (e == hipSuccess && with_tick)
         e = ij::launch_batch_tick(b->d_t, b->d_cases, (int)b->sims.size(), b->d_active, st);
     return e;

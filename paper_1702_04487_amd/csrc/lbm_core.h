@@ -51,7 +51,7 @@ struct SampleRec {
 
 // One lattice of a batch as the batched kernels see it (device memory).
 struct CaseRec {
-    KParams P;              // fb unused: the pulse below gives it per step
+    KParams P;              // P.fb: the body force of the current step (set on the device)
     float* buf[2];          // distribution buffers; buf[0] holds the state at parity 0
     const uint8_t* wall;    // [ny][pitch]
     const uint8_t* plain;   // plain-row table [n_strips][ny]
@@ -114,12 +114,12 @@ struct BatchTiles {
     int n_wide, n_tail, n_gen, n_rows;
     int grid_wide, grid_tail;
 };
-hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int64_t* t_dev,
-                                const int* active, int waves_x, hipStream_t st);
+hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
+                                int waves_x, hipStream_t st);
 // advances the step counter; a case switched off has its two buffers swapped,
 // so that the buffer a step reads is always the one that holds its state
 hipError_t launch_batch_tick(int64_t* t_dev, CaseRec* cases, int n_cases, const int* active, hipStream_t st);
-hipError_t launch_batch_set_time(int64_t* t_dev, int64_t t, hipStream_t st);
+hipError_t launch_batch_set_time(int64_t* t_dev, int64_t t, CaseRec* cases, int n_cases, hipStream_t st);
 hipError_t launch_batch_diag(const CaseRec* cases, int n_cases, int max_nx, int max_ny, int max_ghost, int parity,
                              const int64_t* t_dev, int64_t* n_rec, int* active, hipStream_t st);
 // workgroups of the plain batched kernel that are resident at once on the

@@ -1497,21 +1497,18 @@ __device__ __forceinline__ double case_pulse(const CaseRec& c, int64_t t)
 template <int NW, bool PLAIN>
 __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __restrict__ cases,
                                                            const int4* __restrict__ tiles, int n_tiles,
-                                                           int per_wg, int parity, const int64_t* __restrict__ t_dev,
-                                                           const int* __restrict__ active)
+                                                           int per_wg, int parity, const int* __restrict__ active)
 {
-    const int64_t t = *t_dev;
     const bool single = per_wg == 1;
     const int i0 = blockIdx.x * per_wg, i1 = min(n_tiles, i0 + per_wg);
     for (int i = i0; i < i1; ++i) {
         const int4 tl = tiles[i];
         if (!active[tl.x]) continue;
         const CaseRec& R = cases[tl.x];
-        const KParams P = R.P;
-        const float fb = (float)case_pulse(R, t);
+        const KParams P = R.P;   // P.fb: the case's body force of this step
         const int y0 = tl.z & 0xffff;
         const bool down = single && ((tl.z >> 30) & 1);
-        collide_tile<NW, PLAIN>(P, fb, R.buf[parity], R.buf[1 - parity], R.wall, R.plain, tl.y, tl.w, y0,
+        collide_tile<NW, PLAIN>(P, P.fb, R.buf[parity], R.buf[1 - parity], R.wall, R.plain, tl.y, tl.w, y0,
                                 y0 + ((tl.z >> 16) & 0x3fff), nullptr, down);
     }
 }
@@ -1525,36 +1522,46 @@ __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __rest
 template <int NW>
 __global__ __launch_bounds__(64 * NW) void k_batch_rows(const CaseRec* __restrict__ cases,
                                                         const int4* __restrict__ tiles, int parity,
-                                                        const int64_t* __restrict__ t_dev,
                                                         const int* __restrict__ active)
 {
     const unsigned n = gridDim.x, b = blockIdx.x, xcd = b & 7u;
     const int4 tl = tiles[xcd * (n >> 3) + min(xcd, n & 7u) + (b >> 3)];   // (case, row, first column, 0)
-    if (!active[tl.x]) return;
     const CaseRec& R = cases[tl.x];
     const int x0 = tl.z + 64 * __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (x0 >= R.P.nx) return;
-    const KParams P = R.P;
-    collide_row_wave<false>(P, (float)case_pulse(R, *t_dev), R.buf[parity], R.buf[1 - parity], tl.y, x0, nullptr);
+    // the guard flag and the case's width are read together: one round trip
+    // before the populations
+    if (!active[tl.x] | (x0 >= R.P.nx)) return;
+    const KParams P = R.P;   // P.fb: the case's body force of this step
+    collide_row_wave<false>(P, P.fb, R.buf[parity], R.buf[1 - parity], tl.y, x0, nullptr);
 }
 
-__global__ void k_batch_tick(int64_t* t_dev, CaseRec* __restrict__ cases, int n_cases, const int* __restrict__ active)
+// One workgroup: the step counter moves on, a case the guard froze swaps
+// its buffers (its state stays), and every case's body force of the new
+// step goes to its record (the collide launches read it there instead of
+// evaluating the pulse of Fig. 1 in every wave)
+__global__ __launch_bounds__(1024) void k_batch_tick(int64_t* t_dev, CaseRec* __restrict__ cases, int n_cases,
+                                                      const int* __restrict__ active)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c == 0) t_dev[0] += 1;
-    if (c < n_cases && !active[c]) {
-        float* a = cases[c].buf[0];
-        cases[c].buf[0] = cases[c].buf[1];
-        cases[c].buf[1] = a;
+    const int64_t t1 = t_dev[0] + 1;
+    __syncthreads();   // every thread has read the counter before it moves
+    if (threadIdx.x == 0) t_dev[0] = t1;
+    for (int c = threadIdx.x; c < n_cases; c += blockDim.x) {
+        if (!active[c]) {
+            float* a = cases[c].buf[0];
+            cases[c].buf[0] = cases[c].buf[1];
+            cases[c].buf[1] = a;
+        }
+        cases[c].P.fb = (float)case_pulse(cases[c], t1);
     }
 }
 
-__global__ void k_batch_set_time(int64_t* t_dev, int64_t t)
+__global__ __launch_bounds__(1024) void k_batch_set_time(int64_t* t_dev, int64_t t, CaseRec* __restrict__ cases,
+                                                          int n_cases)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) t_dev[0] = t;
+    if (threadIdx.x == 0) t_dev[0] = t;
+    for (int c = threadIdx.x; c < n_cases; c += blockDim.x) cases[c].P.fb = (float)case_pulse(cases[c], t);
 }
 
-// grid (x blocks of 256 columns, row, case)
 __global__ void k_batch_phi(const CaseRec* __restrict__ cases, int parity)
 {
     const CaseRec& R = cases[blockIdx.z];
@@ -1743,8 +1750,8 @@ int batch_resident_workgroups(int waves_x)
     return e == hipSuccess ? cus * per_cu : 0;
 }
 
-hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int64_t* t_dev,
-                                const int* active, int waves_x, hipStream_t st)
+hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
+                                int waves_x, hipStream_t st)
 {
     if (parity & ~1) return hipErrorInvalidValue;
     // plain launches (one per strip width; persistent when the grid is
@@ -1757,14 +1764,14 @@ hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int p
     if (T.n_rows > 0) {   // row tiles: one workgroup each
         switch (waves_x) {
         case 1:
-            hipLaunchKernelGGL((k_batch_rows<1>), dim3(T.n_rows), dim3(64), 0, st, cases, T.rows, parity, t_dev, active);
+            hipLaunchKernelGGL((k_batch_rows<1>), dim3(T.n_rows), dim3(64), 0, st, cases, T.rows, parity, active);
             break;
         case 2:
-            hipLaunchKernelGGL((k_batch_rows<2>), dim3(T.n_rows), dim3(128), 0, st, cases, T.rows, parity, t_dev,
+            hipLaunchKernelGGL((k_batch_rows<2>), dim3(T.n_rows), dim3(128), 0, st, cases, T.rows, parity,
                                active);
             break;
         case 4:
-            hipLaunchKernelGGL((k_batch_rows<4>), dim3(T.n_rows), dim3(256), 0, st, cases, T.rows, parity, t_dev,
+            hipLaunchKernelGGL((k_batch_rows<4>), dim3(T.n_rows), dim3(256), 0, st, cases, T.rows, parity,
                                active);
             break;
         default:
@@ -1776,20 +1783,20 @@ hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int p
     const int gt = runs(T.n_tail, T.grid_tail, pt);
     if (gt > 0)
         hipLaunchKernelGGL((k_batch_collide<1, true>), dim3(gt), dim3(64), 0, st, cases, T.tail, T.n_tail, pt,
-                           parity, t_dev, active);
+                           parity, active);
     if (gw > 0) {
         switch (waves_x) {
         case 1:
             hipLaunchKernelGGL((k_batch_collide<1, true>), dim3(gw), dim3(64), 0, st, cases, T.wide, T.n_wide, pw,
-                               parity, t_dev, active);
+                               parity, active);
             break;
         case 2:
             hipLaunchKernelGGL((k_batch_collide<2, true>), dim3(gw), dim3(128), 0, st, cases, T.wide, T.n_wide, pw,
-                               parity, t_dev, active);
+                               parity, active);
             break;
         case 4:
             hipLaunchKernelGGL((k_batch_collide<4, true>), dim3(gw), dim3(256), 0, st, cases, T.wide, T.n_wide, pw,
-                               parity, t_dev, active);
+                               parity, active);
             break;
         default:
             return hipErrorInvalidValue;
@@ -1797,20 +1804,19 @@ hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int p
     }
     if (T.n_gen > 0)
         hipLaunchKernelGGL((k_batch_collide<1, false>), dim3(T.n_gen), dim3(64), 0, st, cases, T.gen, T.n_gen, 1,
-                           parity, t_dev, active);
+                           parity, active);
     return hipGetLastError();
 }
 
 hipError_t launch_batch_tick(int64_t* t_dev, CaseRec* cases, int n_cases, const int* active, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_batch_tick, dim3((unsigned)std::max(1, (n_cases + 255) / 256)), dim3(256), 0, st, t_dev,
-                       cases, n_cases, active);
+    hipLaunchKernelGGL(k_batch_tick, dim3(1), dim3(1024), 0, st, t_dev, cases, n_cases, active);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_set_time(int64_t* t_dev, int64_t t, hipStream_t st)
+hipError_t launch_batch_set_time(int64_t* t_dev, int64_t t, CaseRec* cases, int n_cases, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_batch_set_time, dim3(1), dim3(64), 0, st, t_dev, t);
+    hipLaunchKernelGGL(k_batch_set_time, dim3(1), dim3(1024), 0, st, t_dev, t, cases, n_cases);
     return hipGetLastError();
 }
 
