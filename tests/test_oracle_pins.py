@@ -371,6 +371,56 @@ def test_poiseuille_profile(oracle_mod):
     assert np.linalg.norm(u - ua) / np.linalg.norm(ua) < 0.01
 
 
+def test_open_rows_keep_a_fully_developed_channel_flow(oracle_mod):
+    """The "fully developed" open rows (reading R8: the populations entering
+    through the bottom and top rows are copied from the adjacent interior
+    row): a body-force channel flow that does not vary along y is a fixed
+    point of that rule, so an open channel relaxes to the same Poiseuille
+    profile as the periodic one, on every row including the two open ones.
+    A rule that copied from the wrong row, or left the entering populations
+    to streaming, would bend the profile near the ends."""
+    O = oracle_mod
+    w = 32
+    nx, ny = w + 2, 12
+    F = 1e-6
+    p = W.base_params(nx, ny, bc_y=W.BC_OPEN, force_rows=ny, f_pos=F, t_pos=10 ** 9)
+    s = _sim(O, p, W.channel_wall(nx, ny, 1, w))
+    s.init_phi(np.full((ny, nx), s.derived()["phi_star"]))
+    s.step(30000)
+    m = s.moments()
+    x = np.arange(w)
+    ua = F * (x + 0.5) * (w - 0.5 - x) / (2 * s.derived()["n0"] * (0.5 / 3))
+    for y in range(ny):
+        u = m["uy"][y, 1:1 + w]
+        assert np.linalg.norm(u - ua) / np.linalg.norm(ua) < 0.01, y
+    mid = m["uy"][ny // 2, 1:1 + w]
+    assert np.max(np.abs(m["uy"][:, 1:1 + w] - mid)) <= 1e-6 * np.max(np.abs(mid))
+    assert np.max(np.abs(m["ux"][:, 1:1 + w])) <= 1e-9 * np.max(np.abs(mid))
+
+
+def test_open_rows_keep_an_interface_that_crosses_them(oracle_mod):
+    """The open rows' stencil rule (reading R8: phi mirrored across the open
+    edge) and population copy preserve a state that does not vary along y:
+    a planar ink slab whose interfaces run along y, through both open rows,
+    keeps its tanh profile on every row, identical from row to row to
+    round-off."""
+    O = oracle_mod
+    nx, ny = 96, 8
+    p = W.base_params(nx, ny, bc_y=W.BC_OPEN)
+    s = _sim(O, p)
+    xx = np.arange(nx)[None, :].astype(float)
+    dist = np.minimum(xx - 24.3, 71.7 - xx)
+    s.init_distance(np.broadcast_to(dist, (ny, nx)).copy())
+    s.step(2000)
+    phi = s.moments()["phi"]
+    ps = s.derived()["phi_star"]
+    assert np.max(np.abs(phi - phi[ny // 2][None, :])) <= 1e-12 * ps
+    row = phi[ny // 2]
+    i = np.where((row[:-1] < 0) & (row[1:] >= 0))[0][0]
+    assert 2 * ps / (row[i + 1] - row[i]) == pytest.approx(p["width"], rel=0.03)
+    assert i + (-row[i]) / (row[i + 1] - row[i]) == pytest.approx(24.3, abs=0.05)
+
+
 def test_planar_interface_keeps_tanh_profile(oracle_mod):
     """A flat ink slab initialised with phi* tanh(2z/W) stays at that
     profile: width and tension measured on the lattice match W and sigma."""
