@@ -61,6 +61,9 @@ struct ij_batch {
     // graph of graph_steps steps starting at a step that is a multiple of it
     hipStream_t cs = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    // the general pieces run beside the row launch on a second stream
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_len = 0;
@@ -265,8 +268,18 @@ hipError_t one_step(ij_batch* b, int parity, bool diag, bool with_tick, hipStrea
     if (diag)
         e = ij::launch_batch_diag(b->d_cases, (int)b->sims.size(), b->max_nx, b->max_ny, b->max_ghost, parity, b->d_t,
                                   b->d_nrec, b->d_active, st);
-    if (e == hipSuccess)
+    if (e == hipSuccess && b->T.n_rows > 0 && b->T.n_gen > 0) {
+        // the row tiles and the general pieces touch disjoint rows: the
+        // latency-bound pieces run on the side stream beside the row launch
+        e = hipEventRecord(b->ev_fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
+        if (e == hipSuccess) e = ij::launch_batch_general(b->T, b->d_cases, parity, b->d_active, b->waves_x, b->side);
+        if (e == hipSuccess) e = ij::launch_batch_rows(b->T, b->d_cases, parity, b->d_active, b->waves_x, st);
+        if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->side);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join, 0);
+    } else if (e == hipSuccess) {
         e = ij::launch_batch_collide(b->T, b->d_cases, parity, b->d_active, b->waves_x, st);
+    }
     if (e == hipSuccess && with_tick)
         e = ij::launch_batch_tick(b->d_t, b->d_cases, (int)b->sims.size(), b->d_active, st);
     return e;
@@ -437,6 +450,9 @@ ij_status ij_batch_create(const ij_params* cases, int32_t n, ij_batch** out)
         hipHostMalloc(&b->h_active, nb * sizeof(int), hipHostMallocDefault) != hipSuccess)
         return cleanup(IJ_ERR_OOM, "batch table allocation failed");
     if (hipStreamCreateWithFlags(&b->cs, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess)
@@ -451,6 +467,7 @@ void ij_batch_destroy(ij_batch* b)
 {
     if (!b) return;
     if (b->cs) (void)hipStreamSynchronize(b->cs);
+    if (b->side) (void)hipStreamSynchronize(b->side);
     drop_graph(b);
     for (ij_sim* s : b->sims) destroy_sim(s);
     if (b->d_cases) (void)hipFree(b->d_cases);
@@ -465,6 +482,9 @@ void ij_batch_destroy(ij_batch* b)
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
     if (b->staged) (void)hipEventDestroy(b->staged);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+    if (b->side) (void)hipStreamDestroy(b->side);
     if (b->cs) (void)hipStreamDestroy(b->cs);
     delete b;
 }

@@ -116,6 +116,13 @@ struct BatchTiles {
 };
 hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
                                 int waves_x, hipStream_t st);
+// the two halves of launch_batch_collide: the row tiles of the plain rows,
+// and the rest (walked plain tiles, general pieces); independent of each
+// other within a step
+hipError_t launch_batch_rows(const BatchTiles& T, const CaseRec* cases, int parity, const int* active, int waves_x,
+                             hipStream_t st);
+hipError_t launch_batch_general(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
+                                int waves_x, hipStream_t st);
 // advances the step counter; a case switched off has its two buffers swapped,
 // so that the buffer a step reads is always the one that holds its state
 hipError_t launch_batch_tick(int64_t* t_dev, CaseRec* cases, int n_cases, const int* active, hipStream_t st);

@@ -1750,17 +1750,10 @@ int batch_resident_workgroups(int waves_x)
     return e == hipSuccess ? cus * per_cu : 0;
 }
 
-hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
-                                int waves_x, hipStream_t st)
+hipError_t launch_batch_rows(const BatchTiles& T, const CaseRec* cases, int parity, const int* active, int waves_x,
+                             hipStream_t st)
 {
     if (parity & ~1) return hipErrorInvalidValue;
-    // plain launches (one per strip width; persistent when the grid is
-    // smaller than the tile count), then the general pieces
-    auto runs = [&](int n, int grid, int& per_wg) {
-        grid = n > 0 ? std::min(grid, n) : 0;
-        per_wg = grid > 0 ? (n + grid - 1) / grid : 0;
-        return per_wg > 0 ? (n + per_wg - 1) / per_wg : 0;
-    };
     if (T.n_rows > 0) {   // row tiles: one workgroup each
         switch (waves_x) {
         case 1:
@@ -1778,6 +1771,20 @@ hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int p
             return hipErrorInvalidValue;
         }
     }
+    return hipGetLastError();
+}
+
+// the walked plain tiles (one launch per strip width; persistent when the
+// grid is smaller than the tile count), then the general pieces
+hipError_t launch_batch_general(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
+                                int waves_x, hipStream_t st)
+{
+    if (parity & ~1) return hipErrorInvalidValue;
+    auto runs = [&](int n, int grid, int& per_wg) {
+        grid = n > 0 ? std::min(grid, n) : 0;
+        per_wg = grid > 0 ? (n + grid - 1) / grid : 0;
+        return per_wg > 0 ? (n + per_wg - 1) / per_wg : 0;
+    };
     int pw = 0, pt = 0;
     const int gw = runs(T.n_wide, T.grid_wide, pw);
     const int gt = runs(T.n_tail, T.grid_tail, pt);
@@ -1806,6 +1813,13 @@ hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int p
         hipLaunchKernelGGL((k_batch_collide<1, false>), dim3(T.n_gen), dim3(64), 0, st, cases, T.gen, T.n_gen, 1,
                            parity, active);
     return hipGetLastError();
+}
+
+hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
+                                int waves_x, hipStream_t st)
+{
+    const hipError_t e = launch_batch_rows(T, cases, parity, active, waves_x, st);
+    return e != hipSuccess ? e : launch_batch_general(T, cases, parity, active, waves_x, st);
 }
 
 hipError_t launch_batch_tick(int64_t* t_dev, CaseRec* cases, int n_cases, const int* active, hipStream_t st)
