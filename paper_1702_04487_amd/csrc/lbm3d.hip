@@ -272,8 +272,9 @@ __global__ __launch_bounds__(BX* BZ) __attribute__((amdgpu_waves_per_eu(6))) voi
         rsk[k] = (size_t)((unsigned)stencil_row(P, yy) * (unsigned)P.nz + (unsigned)zz);
         xk[k] = xx;
         wk[k] = wall[rsk[k] * P.pitch + xx];
-        s_w[e] = beyond ? kBeyond
-                        : wall[(size_t)((unsigned)wrapi(yy, P.ny) * (unsigned)P.nz + (unsigned)zz) * P.pitch + xx];
+        // short of an open edge the stencil row is the node's own row (wrapped
+        // when periodic), so its wall byte is the destination check's too
+        s_w[e] = beyond ? kBeyond : wk[k];
     }
     float gk[NS][QG];
     uint16_t lk[NS];
