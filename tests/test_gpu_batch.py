@@ -219,7 +219,7 @@ def test_batch_tile_shapes_are_bitwise_equal(gpu_lib):
     cases = _cases()
     runs = []
     for shape in [(1, 16, False, True), (2, 7, True, False), (4, 64, False, False), (4, 32, True, True),
-                  (4, 1, False, False), (2, 1, False, True)]:
+                  (4, 1, False, False), (2, 1, False, True), (1, 1, False, False), (1, 1, True, True)]:
         b = _batch(L, cases)
         b.set_tiling(*shape)
         b.set_graph(10)
@@ -230,3 +230,31 @@ def test_batch_tile_shapes_are_bitwise_equal(gpu_lib):
             assert _same(runs[0].cases[i], other.cases[i]), i
     for b in runs:
         b.close()
+
+
+def test_batch_member_over_4gib_steps_as_alone(gpu_lib):
+    """A member whose buffer takes more than 4 GiB (2048 x 37000 nodes, 4.4 GB
+    per buffer) has its plain rows updated by one-row walked tiles instead of
+    runs, whose byte offsets are 32-bit; it evolves bit for bit as when stepped
+    alone, beside a small member whose rows go to runs."""
+    import torch
+    L = gpu_lib
+    big_nx, big_ny = 2048, 37000
+    pb = W.base_params(big_nx, big_ny, bc_y=W.BC_PERIODIC, tau_ink=0.8, force_rows=big_ny, f_pos=1e-5,
+                       t_pos=10 ** 6, diag_every=K, diag_row0=2)
+    cases = [(pb, W.flat_wall(big_nx, big_ny, (0, 1)),
+              W.discs_distance(big_nx, big_ny, [(300.0, 60.0, 40.0), (1500.0, 36900.0, 50.0), (2040.0, 18000.0, 30.0)])),
+             _cases()[0]]
+    print("member bytes per buffer:", big_ny * (14 * 2048 + 1024) * 4, flush=True)
+    b = _batch(L, cases)
+    b.set_tiling(1, 1, False, False)
+    b.step(3)
+    b.set_tiling(2, 1, False, True)
+    b.step(2)
+    singles = _singles(L, cases, 5)
+    for i, (bc, sc) in enumerate(zip(b.cases, singles)):
+        assert bc.check() == L.IJ_OK and sc.check() == L.IJ_OK, i
+        assert _same(bc, sc), i
+    b.close()
+    del b, singles
+    torch.cuda.empty_cache()
