@@ -44,6 +44,40 @@ __device__ __forceinline__ double phi_of(float g0, float g1, float g2, float g3,
     return ((((double)g1 + (double)g2) + ((double)g3 + (double)g4)) + (double)lo) + (double)g0;
 }
 
+// Accesses through the global address space (at a uniform base plus a
+// 32-bit byte offset, or at an element index).  A pointer read from a case
+// record is generic to the compiler; generic (flat) accesses need a 64-bit
+// address per lane and are counted with the scalar loads, so that waiting for
+// one waits for the other.  Every buffer here is in global memory.
+typedef __attribute__((address_space(1))) char gchar_t;
+__device__ __forceinline__ float gld(const float* base, unsigned bo)
+{
+    return *reinterpret_cast<const __attribute__((address_space(1))) float*>((const gchar_t*)base + bo);
+}
+__device__ __forceinline__ uint16_t gldh(const uint16_t* base, unsigned bo)
+{
+    return *reinterpret_cast<const __attribute__((address_space(1))) uint16_t*>((const gchar_t*)base + bo);
+}
+__device__ __forceinline__ void gst(float* base, unsigned bo, float v)
+{
+    *reinterpret_cast<__attribute__((address_space(1))) float*>((gchar_t*)base + bo) = v;
+}
+__device__ __forceinline__ void gsth(uint16_t* base, unsigned bo, uint16_t v)
+{
+    *reinterpret_cast<__attribute__((address_space(1))) uint16_t*>((gchar_t*)base + bo) = v;
+}
+
+template <class T>
+__device__ __forceinline__ T gat(const T* p, size_t i)
+{
+    return reinterpret_cast<const __attribute__((address_space(1))) T*>((const gchar_t*)p)[i];
+}
+template <class T>
+__device__ __forceinline__ void gput(T* p, size_t i, T v)
+{
+    reinterpret_cast<__attribute__((address_space(1))) T*>((gchar_t*)p)[i] = v;
+}
+
 // Wetting ghost of a solid node (Results, contact-angle wall; Cahn wetting):
 // mean of phi over its fluid axis neighbours (E, N, W, S order), or over its
 // fluid diagonal neighbours (NE, NW, SW, SE) when it has none on the axes,
@@ -223,7 +257,7 @@ __device__ __forceinline__ uint8_t mask_at(const KParams& P, const uint8_t* wall
         if (P.bc_open) return 3;
         y = y < 0 ? y + P.ny : y - P.ny;
     }
-    return wall[(unsigned)y * P.pitch + x];
+    return gat(wall, (unsigned)y * P.pitch + x);
 }
 
 // index of population i of node (x, y) in a buffer
@@ -287,13 +321,13 @@ __device__ __forceinline__ void stream_one(const StreamCtx& c, float hv, float g
     const int wx = fl ? tx : c.x, wy = fl ? ty : c.y;
     const float v = IS_G ? hv + P.omq * (fl ? g_dest : g_self) : hv;
     const int pl = IS_G ? 9 + d : d;
-    c.B[pidx(P, pl, wx, wy)] = v;
+    gput(c.B, pidx(P, pl, wx, wy), v);
     if (P.bc_open) {
         const int cyd = fl ? DY : -DY;
         if (cyd > 0 && wy == 1 && open_fluid(0, fl ? DX : 0))
-            c.B[pidx(P, pl, wx, 0)] = v;
+            gput(c.B, pidx(P, pl, wx, 0), v);
         if (cyd < 0 && wy == P.ny - 2 && open_fluid(1, fl ? DX : 0))
-            c.B[pidx(P, pl, wx, P.ny - 1)] = v;
+            gput(c.B, pidx(P, pl, wx, P.ny - 1), v);
     }
 }
 
@@ -329,10 +363,10 @@ __device__ __forceinline__ void stream_shifted(const ShiftCtx& c, float v, float
     }
     const int pl = IS_G ? 9 + I : I;
     auto put = [&](int plane_idx, int cyd, int wx, int wy, int dxo, float val) {
-        c.B[pidx(P, plane_idx, wx, wy)] = val;
+        gput(c.B, pidx(P, plane_idx, wx, wy), val);
         if (P.bc_open) {
-            if (cyd > 0 && wy == 1 && open_fluid(0, dxo)) c.B[pidx(P, plane_idx, wx, 0)] = val;
-            if (cyd < 0 && wy == P.ny - 2 && open_fluid(1, dxo)) c.B[pidx(P, plane_idx, wx, P.ny - 1)] = val;
+            if (cyd > 0 && wy == 1 && open_fluid(0, dxo)) gput(c.B, pidx(P, plane_idx, wx, 0), val);
+            if (cyd < 0 && wy == P.ny - 2 && open_fluid(1, dxo)) gput(c.B, pidx(P, plane_idx, wx, P.ny - 1), val);
         }
     };
     // receive: this lane's column at row y + DY, pushed from column x - DX
@@ -359,9 +393,9 @@ __device__ __forceinline__ void phi_node(const KParams& P, const float* __restri
                                          const uint8_t* __restrict__ wall, double* __restrict__ phi, int x, int y)
 {
     const unsigned k = (unsigned)y * P.pitch + x;
-    if (wall[k]) return;
-    phi[k] = phi_of(A[pidx(P, 9, x, y)], A[pidx(P, 10, x, y)], A[pidx(P, 11, x, y)], A[pidx(P, 12, x, y)],
-                    A[pidx(P, 13, x, y)], bf16_to_float(lo_row(A, P, y)[x]));
+    if (gat(wall, k)) return;
+    gput(phi, k, phi_of(gat(A, pidx(P, 9, x, y)), gat(A, pidx(P, 10, x, y)), gat(A, pidx(P, 11, x, y)),
+                        gat(A, pidx(P, 12, x, y)), gat(A, pidx(P, 13, x, y)), bf16_to_float(gat(lo_row(A, P, y), x))));
 }
 
 __global__ void k_phi_from_g(KParams P, const float* __restrict__ A, const uint8_t* __restrict__ wall,
@@ -388,11 +422,11 @@ __device__ __forceinline__ void ghost_node(const KParams& P, int2 node, const ui
             const int xx = wrapx(x + dx[k], P.nx);
             int yy = y + dy[k];
             yy = yy < 0 ? yy + P.ny : (yy >= P.ny ? yy - P.ny : yy);
-            v[k] = phi[(unsigned)yy * P.pitch + xx];
+            v[k] = gat(phi, (unsigned)yy * P.pitch + xx);
         }
     }
     const unsigned k0 = (unsigned)y * P.pitch + x;
-    phi[k0] = ghost_value(v, m, P.wet[wall[k0]]);
+    gput(phi, k0, ghost_value(v, m, P.wet[gat(wall, k0)]));
 }
 
 __global__ void k_ghost(KParams P, const int2* __restrict__ list, int n, const uint8_t* __restrict__ wall,
@@ -408,15 +442,15 @@ __device__ __forceinline__ void load_stencil(const KParams& P, const double* __r
     const int xe = wrapx(x + 1, P.nx), xw = wrapx(x - 1, P.nx);
     const int yn = stencil_row(y + 1, P), ys = stencil_row(y - 1, P);
     const unsigned r0 = (unsigned)y * P.pitch, rn = (unsigned)yn * P.pitch, rs = (unsigned)ys * P.pitch;
-    st[0] = phi[r0 + x];
-    st[1] = phi[r0 + xe];
-    st[2] = phi[rn + x];
-    st[3] = phi[r0 + xw];
-    st[4] = phi[rs + x];
-    st[5] = phi[rn + xe];
-    st[6] = phi[rn + xw];
-    st[7] = phi[rs + xw];
-    st[8] = phi[rs + xe];
+    st[0] = gat(phi, r0 + x);
+    st[1] = gat(phi, r0 + xe);
+    st[2] = gat(phi, rn + x);
+    st[3] = gat(phi, r0 + xw);
+    st[4] = gat(phi, rs + x);
+    st[5] = gat(phi, rn + xe);
+    st[6] = gat(phi, rn + xw);
+    st[7] = gat(phi, rs + xw);
+    st[8] = gat(phi, rs + xe);
 }
 
 // Reference collide-stream: one node per thread, phi~ from the phi field,
@@ -614,15 +648,15 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
     const int hidx = t < 2 ? t : wv + 2 + (t - 2);   // LDS column of the halo of threads 0..3
 
     for (int i = t; i < y1 - y0; i += BW)
-        s_mine[i] = (plain_rows[(size_t)strip * P.ny + y0 + i] != 0) == PLAIN;
+        s_mine[i] = (gat(plain_rows, (size_t)strip * P.ny + y0 + i) != 0) == PLAIN;
 
     // row bases (uniform over the workgroup: 64-bit) and 32-bit byte offsets
     // of population i of column xx within a row
     auto arow = [&](int yy) { return A + (size_t)(unsigned)yy * P.rs; };
     auto brow = [&](int yy) { return B + (size_t)(unsigned)yy * P.rs; };
     auto boff = [&](int i, int xx) -> unsigned { return ((unsigned)i * (unsigned)P.pitch + (unsigned)xx) << 2; };
-    auto ldf = [](const float* base, unsigned bo) { return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + bo); };
-    auto stf = [](float* base, unsigned bo, float v) { *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + bo) = v; };
+    auto ldf = [](const float* base, unsigned bo) { return gld(base, bo); };
+    auto stf = [](float* base, unsigned bo, float v) { gst(base, bo, v); };
 
     // two register sets for loads in flight: raw rows (g, remainder bits,
     // mask; halo columns) and collide rows (f)
@@ -651,14 +685,14 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
         const unsigned k = (unsigned)ry * P.pitch + xc;
         const unsigned kh = (unsigned)ry * P.pitch + hx;
         const float* Ar = arow(ry);
-        m = wall[k];
-        mh = wall[kh];
+        m = gat(wall, k);
+        mh = gat(wall, kh);
 #pragma unroll
         for (int i = 0; i < 5; ++i) g[i] = ldf(Ar, boff(9 + i, xc));
 #pragma unroll
         for (int i = 0; i < 5; ++i) gh[i] = ldf(Ar, boff(9 + i, hx));
-        lo = lo_row(A, P, ry)[xc];
-        loh = lo_row(A, P, ry)[hx];
+        lo = gat(lo_row(A, P, ry), xc);
+        loh = gat(lo_row(A, P, ry), hx);
     };
 
     // rows y0-2 .. y1+1 pass through the ring, upwards, or downwards when
@@ -772,7 +806,7 @@ __device__ __forceinline__ void collide_tile(const KParams& P, float fb, const f
                 float* Bc = brow(rc);
                 stf(Bc, boff(0, x), fs[0]);
                 stf(Bc, boff(9, x), g0h);
-                lo_row(B, P, rc)[x] = g0l;
+                gput(lo_row(B, P, rc), x, g0l);
                 if constexpr (!PLAIN) {
 #pragma unroll
                     for (int i = 1; i < 9; ++i) s_out[i - 1][jo] = fs[i];
@@ -1052,28 +1086,6 @@ __device__ __forceinline__ void collide_row_wave(const KParams& P, float fb, con
         const DiagRow r = sample_piece(dterm);
         if (lane == 0) parts[(size_t)(x0 >> 6) * P.ny + y] = r;
     }
-}
-
-// Accesses through the global address space at a uniform base plus a 32-bit
-// byte offset.  A pointer read from a case record is generic to the
-// compiler; generic (flat) accesses need a 64-bit address per lane and are
-// counted with the scalar loads, so that waiting for one waits for the other.
-typedef __attribute__((address_space(1))) char gchar_t;
-__device__ __forceinline__ float gld(const float* base, unsigned bo)
-{
-    return *reinterpret_cast<const __attribute__((address_space(1))) float*>((const gchar_t*)base + bo);
-}
-__device__ __forceinline__ uint16_t gldh(const uint16_t* base, unsigned bo)
-{
-    return *reinterpret_cast<const __attribute__((address_space(1))) uint16_t*>((const gchar_t*)base + bo);
-}
-__device__ __forceinline__ void gst(float* base, unsigned bo, float v)
-{
-    *reinterpret_cast<__attribute__((address_space(1))) float*>((gchar_t*)base + bo) = v;
-}
-__device__ __forceinline__ void gsth(uint16_t* base, unsigned bo, uint16_t v)
-{
-    *reinterpret_cast<__attribute__((address_space(1))) uint16_t*>((gchar_t*)base + bo) = v;
 }
 
 // A double held by lane l of the wave (l uniform)
@@ -1438,11 +1450,11 @@ __device__ __forceinline__ void diag_row(const KParams& P, float fb, const float
             const int x = k * 64 + lane;
             if (x < P.nx) {
                 const unsigned kk = (unsigned)y * P.pitch + x;
-                if (!wall[kk]) {
+                if (!gat(wall, kk)) {
                     float f[9];
                     double st[9], Fx, Fy;
 #pragma unroll
-                    for (int i = 0; i < 9; ++i) f[i] = A[pidx(P, i, x, y)];
+                    for (int i = 0; i < 9; ++i) f[i] = gat(A, pidx(P, i, x, y));
                     load_stencil(P, phi, x, y, st);
                     Macro m;
                     node_macro(P, f, st, y < P.force_rows ? fb : 0.f, m, Fx, Fy);
