@@ -307,9 +307,8 @@ ij_status ij_batch_set_graph(ij_batch *b, int32_t steps_per_graph);
  * one-wave launch) instead of a partly idle full-width strip; persistent:
  * nonzero runs as many workgroups as are resident at once, each over a
  * contiguous run of tiles, zero one workgroup per tile.  With one row per
- * workgroup the plain rows go to runs of 64 nodes in row-major order, one
- * per wave and waves_x per workgroup (rows that are plain over their whole
- * width follow each other without idle lanes).  Default (4, 1, 0, 1). */
+ * workgroup the plain rows go to pieces of 64 columns, one per wave and
+ * waves_x per workgroup.  Default (4, 1, 0, 1). */
 ij_status ij_batch_set_tiling(ij_batch *b, int32_t waves_x, int32_t rows_per_block, int32_t mixed_strips,
                               int32_t persistent);
 ij_status ij_batch_get_tiling(const ij_batch *b, int32_t *waves_x, int32_t *rows_per_block,

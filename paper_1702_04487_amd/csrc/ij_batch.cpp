@@ -145,40 +145,14 @@ ij_status build_tiles(ij_batch* b)
     for (size_t c = 0; c < b->sims.size(); ++c) {
         const ij_sim* s = b->sims[c];
         if (b->rows_per_block == 1) {
-            // runs of at most 64 plain nodes, row-major: over a band of rows
-            // that are plain over their whole width they go on from one row
-            // to the next; in other rows they stay within the plain strips
-            const bool small = (uint64_t)s->ny * s->K.rs * sizeof(float) < (uint64_t(1) << 32);
-            const bool wrap = small && s->nx >= 64;
-            auto full = [&](int y) {
-                for (int k = 0; k < s->n_strips; ++k)
-                    if (!s->plain_host[(size_t)k * s->ny + y]) return false;
-                return true;
-            };
-            for (int y = 0; y < s->ny;) {
-                if (wrap && full(y)) {
-                    int y1 = y + 1;
-                    while (y1 < s->ny && full(y1)) ++y1;
-                    const int64_t band = (int64_t)(y1 - y) * s->nx;
-                    for (int64_t q = 0; q < band; q += 64)
-                        lists[3].push_back(make_int4((int)c, y + (int)(q / s->nx), (int)(q % s->nx),
-                                                     (int)std::min<int64_t>(64, band - q)));
-                    y = y1;
-                    continue;
-                }
+            // pieces of 64 columns of every plain (row, strip) of the case, row-major
+            for (int y = 0; y < s->ny; ++y)
                 for (int k = 0; k < s->n_strips; ++k) {
                     if (!s->plain_host[(size_t)k * s->ny + y]) continue;
-                    const int x0 = s->strip_x0[(size_t)k];
-                    if (!small) {   // the runs' byte offsets are 32-bit: a one-row walked plain tile
-                        lists[k < s->n_wide ? 0 : 1].push_back(make_int4((int)c, k, y | (1 << 16), x0));
-                        continue;
-                    }
                     const int x1 = k + 1 < s->n_strips ? s->strip_x0[(size_t)k + 1] : s->nx;
-                    for (int x = x0; x < x1; x += 64)
+                    for (int x = s->strip_x0[(size_t)k]; x < x1; x += 64)
                         lists[3].push_back(make_int4((int)c, y, x, std::min(64, x1 - x)));
                 }
-                ++y;
-            }
         } else
         // plain tiles that hold a plain row (a block of rows that all sit
         // beside solid nodes, such as a nozzle channel, is the general

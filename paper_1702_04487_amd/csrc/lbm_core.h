@@ -106,13 +106,9 @@ hipError_t launch_diag(const KParams& P, const float* A, const uint8_t* wall, co
 // (one wave); at most kMaxRowsPerBlock rows each.  The plain launches run
 // grid_wide / grid_tail workgroups, each over a contiguous run of tiles (a
 // grid of one workgroup per tile when it equals the tile count).
-// With rows_per_block 1 the plain rows go to runs (case, row, first column,
-// nodes) of at most 64 nodes in row-major order, one wave each and waves_x
-// per workgroup, instead of walked plain tiles (n_wide = n_tail = 0).  A run
-// may go on from the last column of its row to column 0 of the next only
-// where both rows are plain over their whole width and nx >= 64; elsewhere
-// runs stay within a plain strip of a row.  The plain rows of a case whose
-// buffer takes 4 GiB or more go to walked plain tiles of one row instead.
+// With rows_per_block 1 the plain rows go to pieces (case, row, first column,
+// nodes) of 64 columns of the plain strips of each row, one wave each and
+// waves_x per workgroup, instead of walked plain tiles (n_wide = n_tail = 0).
 struct BatchTiles {
     const int4 *wide, *tail, *gen, *rows;
     int n_wide, n_tail, n_gen, n_rows;

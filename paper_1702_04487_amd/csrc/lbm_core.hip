@@ -961,7 +961,7 @@ __device__ __forceinline__ double dfrom_right(double v)
 // workgroup of NW waves covers a strip of 64 NW columns.
 // One wave: the 64 columns from x0 (< nx) of the plain row y, with the
 // body force fb of the step.
-template <bool SAMPLE>
+template <bool SAMPLE, bool AS_GLOBAL = false>
 __device__ __forceinline__ void collide_row_wave(const KParams& P, float fb, const float* __restrict__ A,
                                                  float* __restrict__ B, int y, int x0, DiagRow* __restrict__ parts)
 {
@@ -982,8 +982,20 @@ __device__ __forceinline__ void collide_row_wave(const KParams& P, float fb, con
     // 32-bit byte offset of this lane's column (one per lane, shared by every
     // access); the population rows are uniform bases
     const unsigned xo = (unsigned)xc << 2, xo2 = (unsigned)xc << 1;
-    auto ldf = [](const float* base, unsigned bo) { return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + bo); };
-    auto ldh = [](const uint16_t* base, unsigned bo) { return *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(base) + bo); };
+    // AS_GLOBAL: A and B were read from memory (a case record), so the
+    // accesses name the global address space themselves
+    auto ldf = [](const float* base, unsigned bo) {
+        if constexpr (AS_GLOBAL) return gld(base, bo);
+        else return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + bo);
+    };
+    auto ldh = [](const uint16_t* base, unsigned bo) {
+        if constexpr (AS_GLOBAL) return gldh(base, bo);
+        else return *reinterpret_cast<const uint16_t*>(reinterpret_cast<const char*>(base) + bo);
+    };
+    auto at = [](const auto* base, size_t i) {
+        if constexpr (AS_GLOBAL) return gat(base, i);
+        else return base[i];
+    };
     float f[9], gs[5], gc[5], gn[5];
     uint16_t los, loc, lon;
 #pragma unroll
@@ -999,13 +1011,13 @@ __device__ __forceinline__ void collide_row_wave(const KParams& P, float fb, con
     lon = ldh(lo_row(A, P, yn), xo2);
     // halo columns: uniform addresses
     auto halo_phi = [&](const float* R, int yy, int hx) {
-        return phi_of(R[9 * pch + hx], R[10 * pch + hx], R[11 * pch + hx], R[12 * pch + hx], R[13 * pch + hx],
-                      bf16_to_float(lo_row(A, P, yy)[hx]));
+        return phi_of(at(R, 9 * pch + hx), at(R, 10 * pch + hx), at(R, 11 * pch + hx), at(R, 12 * pch + hx),
+                      at(R, 13 * pch + hx), bf16_to_float(at(lo_row(A, P, yy), hx)));
     };
     const double pls = halo_phi(As, ys, xl), plc = halo_phi(Ac, y, xl), pln = halo_phi(An, yn, xl);
     const double prs = halo_phi(As, ys, xr), prc = halo_phi(Ac, y, xr), prn = halo_phi(An, yn, xr);
-    const float g1r = Ac[10 * pch + xr];   // pre-collision g_1 of the column past the piece, row y
-    const float g3l = Ac[12 * pch + xl];   // pre-collision g_3 of the column before it
+    const float g1r = at(Ac, 10 * pch + xr);   // pre-collision g_1 of the column past the piece, row y
+    const float g3l = at(Ac, 12 * pch + xl);   // pre-collision g_3 of the column before it
 
     const double ps = phi_of(gs[0], gs[1], gs[2], gs[3], gs[4], bf16_to_float(los));
     const double pc = phi_of(gc[0], gc[1], gc[2], gc[3], gc[4], bf16_to_float(loc));
@@ -1044,14 +1056,18 @@ __device__ __forceinline__ void collide_row_wave(const KParams& P, float fb, con
     const float r3 = from_right(fs[3]), r6 = from_right(fs[6]), r7 = from_right(fs[7]);
     const float rh3 = from_right(h[3]);
     if (active) {
-        auto stf = [](float* base, unsigned bo, float v) { *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + bo) = v; };
+        auto stf = [](float* base, unsigned bo, float v) {
+            if constexpr (AS_GLOBAL) gst(base, bo, v);
+            else *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + bo) = v;
+        };
         float* Bs = B + (size_t)(unsigned)ys * P.rs;
         float* Bc = B + (size_t)(unsigned)y * P.rs;
         float* Bn = B + (size_t)(unsigned)yn * P.rs;
         const unsigned wo = (unsigned)x << 2;
         stf(Bc, wo, fs[0]);
         stf(Bc + 9 * pch, wo, g0h);
-        *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lo_row(B, P, y)) + ((unsigned)x << 1)) = g0l;
+        if constexpr (AS_GLOBAL) gsth(lo_row(B, P, y), (unsigned)x << 1, g0l);
+        else *reinterpret_cast<uint16_t*>(reinterpret_cast<char*>(lo_row(B, P, y)) + ((unsigned)x << 1)) = g0l;
         stf(Bn + 2 * pch, wo, fs[2]);
         stf(Bs + 4 * pch, wo, fs[4]);
         stf(Bn + 11 * pch, wo, h[2] + P.omq * gn[2]);
@@ -1085,156 +1101,6 @@ __device__ __forceinline__ void collide_row_wave(const KParams& P, float fb, con
         // this wave's 64 columns of row y are piece x0 / 64
         const DiagRow r = sample_piece(dterm);
         if (lane == 0) parts[(size_t)(x0 >> 6) * P.ny + y] = r;
-    }
-}
-
-// A double held by lane l of the wave (l uniform)
-__device__ __forceinline__ double dlane(double v, int l)
-{
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                            __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-
-// A run of plain nodes: one wave updates the n (1..64) nodes that follow
-// each other in row-major order from (y0, x0), with the body force fb.  A run
-// that passes the last column of row y0 goes on at column 0 of row y0 + 1
-// (lanes k = nx - x0 on); both rows of such a run are plain over their whole
-// width, and nx >= 64, so a run splits at most once.  Each node gets the
-// update of collide_row_wave, from the same values: the lanes beside the split
-// take their neighbours across the periodic x edge from the lanes of the other
-// row (lane k holds column 0 of rows y0 .. y0 + 2, lane k - 1 column nx - 1 of
-// rows y0 - 1 .. y0 + 1), the corners of that 3 x 2 block from two more halo
-// nodes, and they store across the edge as the end lanes of a row do.  Byte
-// offsets within the buffer are 32-bit (the caller keeps runs to buffers
-// below 4 GiB).
-__device__ __forceinline__ void collide_run_wave(const KParams& P, float fb, const float* __restrict__ A,
-                                                 float* __restrict__ B, int y0, int x0, int n)
-{
-    const int lane = threadIdx.x & 63;
-    const int k = P.nx - x0;                   // first lane of row y0 + 1
-    const bool split = n > k;
-    const bool active = lane < n;
-    const int li = min(lane, n - 1);           // lanes past the run load its last node (unused)
-    const bool up = li >= k;
-    const int y = up ? y0 + 1 : y0;
-    const int x = up ? li - k : x0 + li;
-    const int ys = y == 0 ? P.ny - 1 : y - 1, yn = y + 1 == P.ny ? 0 : y + 1;   // periodic (plain rows)
-    const unsigned rsb = P.rs << 2, pch = (unsigned)P.pitch;
-    // byte offsets of this lane's column in its three lattice rows (float
-    // rows, then the 16-bit remainder row); the population rows are uniform bases
-    const unsigned os = (unsigned)ys * rsb + ((unsigned)x << 2), oc = (unsigned)y * rsb + ((unsigned)x << 2),
-                   on = (unsigned)yn * rsb + ((unsigned)x << 2);
-    const unsigned hs = (unsigned)ys * rsb + ((unsigned)x << 1), hc = (unsigned)y * rsb + ((unsigned)x << 1),
-                   hn = (unsigned)yn * rsb + ((unsigned)x << 1);
-    const uint16_t* lo0 = reinterpret_cast<const uint16_t*>(A + (size_t)kFloatPlanes * pch);
-    float f[9], gs[5], gc[5], gn[5];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = gld(A + i * pch, oc);
-#pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        gs[i] = gld(A + (9 + i) * pch, os);
-        gc[i] = gld(A + (9 + i) * pch, oc);
-        gn[i] = gld(A + (9 + i) * pch, on);
-    }
-    const uint16_t los = gldh(lo0, hs), loc = gldh(lo0, hc), lon = gldh(lo0, hn);
-
-    // halo nodes (uniform addresses): column xl of rows y0 - 1 .. y0 + 1 before
-    // the first lane, column xr of rows ye - 1 .. ye + 1 past the last (row ye)
-    auto wrapy = [&](int yy) { return yy < 0 ? yy + P.ny : (yy >= P.ny ? yy - P.ny : yy); };
-    auto rowp = [&](int yy) { return A + (size_t)(unsigned)yy * P.rs; };
-    auto halo_phi = [&](int yy, int hx) {
-        const float* R = rowp(yy);
-        const unsigned hb = (unsigned)hx << 2;
-        return phi_of(gld(R + 9 * pch, hb), gld(R + 10 * pch, hb), gld(R + 11 * pch, hb), gld(R + 12 * pch, hb),
-                      gld(R + 13 * pch, hb), bf16_to_float(gldh(lo_row(A, P, yy), (unsigned)hx << 1)));
-    };
-    const int ye = split ? y0 + 1 : y0, xe = split ? n - 1 - k : x0 + n - 1;
-    const int xl = x0 == 0 ? P.nx - 1 : x0 - 1, xr = xe + 1 == P.nx ? 0 : xe + 1;
-    const double pls = halo_phi(wrapy(y0 - 1), xl), plc = halo_phi(y0, xl), pln = halo_phi(wrapy(y0 + 1), xl);
-    const double prs = halo_phi(wrapy(ye - 1), xr), prc = halo_phi(ye, xr), prn = halo_phi(wrapy(ye + 1), xr);
-    const float g1r = gld(rowp(ye) + 10 * pch, (unsigned)xr << 2);   // pre-collision g_1 past the run, row ye
-    const float g3l = gld(rowp(y0) + 12 * pch, (unsigned)xl << 2);   // pre-collision g_3 before it, row y0
-
-    const double ps = phi_of(gs[0], gs[1], gs[2], gs[3], gs[4], bf16_to_float(los));
-    const double pc = phi_of(gc[0], gc[1], gc[2], gc[3], gc[4], bf16_to_float(loc));
-    const double pn = phi_of(gn[0], gn[1], gn[2], gn[3], gn[4], bf16_to_float(lon));
-
-    // the split: lanes k - 1 (column nx - 1 of row y0) and k (column 0 of row y0 + 1)
-    const int ka = split ? k - 1 : 0, kb = split ? k : 0;
-    double sx = 0.0, sy = 0.0;   // phi at (0, y0 - 1) and (nx - 1, y0 + 2)
-    if (split) {
-        sx = halo_phi(wrapy(y0 - 1), 0);
-        sy = halo_phi(wrapy(y0 + 2), P.nx - 1);
-    }
-    const double kb_s = dlane(ps, kb), kb_c = dlane(pc, kb), ka_c = dlane(pc, ka), ka_n = dlane(pn, ka);
-    const float g1s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gs[1]), kb));   // old g_1 at (0, y0)
-    const float g3s = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gn[3]), ka));   // old g_3 at (nx - 1, y0 + 1)
-    const bool lsplit = split && lane == k, rsplit = split && lane == k - 1;
-    const bool ledge = lane == 0 || lsplit, redge = lane == n - 1 || rsplit;
-    double st[9];
-    st[0] = pc;
-    st[2] = pn;
-    st[4] = ps;
-    {
-        const double l_s = dfrom_left(ps), l_c = dfrom_left(pc), l_n = dfrom_left(pn);
-        const double r_s = dfrom_right(ps), r_c = dfrom_right(pc), r_n = dfrom_right(pn);
-        st[1] = lane == n - 1 ? prc : (rsplit ? kb_s : r_c);
-        st[5] = lane == n - 1 ? prn : (rsplit ? kb_c : r_n);
-        st[8] = lane == n - 1 ? prs : (rsplit ? sx : r_s);
-        st[3] = lane == 0 ? plc : (lsplit ? ka_n : l_c);
-        st[6] = lane == 0 ? pln : (lsplit ? sy : l_n);
-        st[7] = lane == 0 ? pls : (lsplit ? ka_c : l_s);
-    }
-
-    float fs[9], h[5], g0h = 0.f;
-    uint16_t g0l = 0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) fs[i] = 0.f;
-#pragma unroll
-    for (int i = 0; i < 5; ++i) h[i] = 0.f;
-    if (active) {
-        Macro mac;
-        node_collide(P, f, gc, bf16_to_float(loc), st, y < P.force_rows ? fb : 0.f, fs, h, g0h, g0l, mac);
-    }
-    // the populations moving in x come from the neighbouring lanes
-    const float l1 = from_left(fs[1]), l5 = from_left(fs[5]), l8 = from_left(fs[8]);
-    const float lh1 = from_left(h[1]);
-    const float r3 = from_right(fs[3]), r6 = from_right(fs[6]), r7 = from_right(fs[7]);
-    const float rh3 = from_right(h[3]);
-    if (active) {
-        gst(B, oc, fs[0]);
-        gst(B + 9 * pch, oc, g0h);
-        gsth(reinterpret_cast<uint16_t*>(B + (size_t)kFloatPlanes * pch), hc, g0l);
-        gst(B + 2 * pch, on, fs[2]);
-        gst(B + 4 * pch, os, fs[4]);
-        gst(B + 11 * pch, on, h[2] + P.omq * gn[2]);
-        gst(B + 13 * pch, os, h[4] + P.omq * gs[4]);
-        if (!ledge) {                          // pusher x-1 is in this wave, same row
-            gst(B + 1 * pch, oc, l1);
-            gst(B + 5 * pch, on, l5);
-            gst(B + 8 * pch, os, l8);
-            gst(B + 10 * pch, oc, lh1 + P.omq * gc[1]);
-        } else {                               // the first lane of a row stores across its left edge
-            const int xw = x == 0 ? P.nx - 1 : x - 1;
-            const unsigned d = ((unsigned)xw << 2) - ((unsigned)x << 2);
-            gst(B + 3 * pch, oc + d, fs[3]);
-            gst(B + 6 * pch, on + d, fs[6]);
-            gst(B + 7 * pch, os + d, fs[7]);
-            gst(B + 12 * pch, oc + d, h[3] + P.omq * (lane == 0 ? g3l : g3s));
-        }
-        if (!redge) {                          // pusher x+1 is in this wave, same row
-            gst(B + 3 * pch, oc, r3);
-            gst(B + 6 * pch, on, r6);
-            gst(B + 7 * pch, os, r7);
-            gst(B + 12 * pch, oc, rh3 + P.omq * gc[3]);
-        } else {                               // the last lane of a row stores across its right edge
-            const int xw = x + 1 == P.nx ? 0 : x + 1;
-            const unsigned d = ((unsigned)xw << 2) - ((unsigned)x << 2);
-            gst(B + 1 * pch, oc + d, fs[1]);
-            gst(B + 5 * pch, on + d, fs[5]);
-            gst(B + 8 * pch, os + d, fs[8]);
-            gst(B + 10 * pch, oc + d, h[1] + P.omq * (lane == n - 1 ? g1r : g1s));
-        }
     }
 }
 
@@ -1697,26 +1563,26 @@ __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __rest
     }
 }
 
-// The plain rows of every case of a batch as runs of at most 64 nodes
-// (case, row, first column, nodes; see collide_run_wave), listed case by case
-// in row-major order: workgroup g takes runs NW g .. NW g + NW - 1, one per
-// wave, and XCD x (workgroup b % 8) takes the x-th contiguous range of
-// workgroups, so that neighbouring rows of a case share one L2.
+// The plain rows of every case of a batch: pieces (case, row, first column,
+// nodes) of 64 columns of a plain strip of a row, one per wave (the update of
+// collide_row_wave), listed case by case, row-major: workgroup g takes pieces
+// NW g .. NW g + NW - 1, and XCD x (workgroup b % 8) takes the x-th contiguous
+// range of workgroups, so that neighbouring rows of a case share one L2.
 template <int NW>
 __global__ __launch_bounds__(64 * NW) void k_batch_rows(const CaseRec* __restrict__ cases,
-                                                        const int4* __restrict__ runs, int n_runs, int parity,
+                                                        const int4* __restrict__ pieces, int n_pieces, int parity,
                                                         const int* __restrict__ active)
 {
     const unsigned n = gridDim.x, b = blockIdx.x, xcd = b & 7u;
     const unsigned g = xcd * (n >> 3) + min(xcd, n & 7u) + (b >> 3);
     const unsigned i = g * NW + (unsigned)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (i >= (unsigned)n_runs) return;
-    const int4 r = runs[i];
+    if (i >= (unsigned)n_pieces) return;
+    const int4 r = pieces[i];
     const CaseRec& R = cases[r.x];
     // the guard flag is read with the record: one round trip before the populations
     if (!active[r.x]) return;
     const KParams P = R.P;   // P.fb: the case's body force of this step
-    collide_run_wave(P, P.fb, R.buf[parity], R.buf[1 - parity], r.y, r.z, r.w);
+    collide_row_wave<false, true>(P, P.fb, R.buf[parity], R.buf[1 - parity], r.y, r.z, nullptr);
 }
 
 // One workgroup: the step counter moves on, a case the guard froze swaps
@@ -1938,7 +1804,7 @@ hipError_t launch_batch_rows(const BatchTiles& T, const CaseRec* cases, int pari
                              hipStream_t st)
 {
     if (parity & ~1) return hipErrorInvalidValue;
-    if (T.n_rows > 0) {   // runs: one per wave
+    if (T.n_rows > 0) {   // pieces: one per wave
         const unsigned n = (unsigned)T.n_rows;
         switch (waves_x) {
         case 1:

@@ -234,9 +234,9 @@ def test_batch_tile_shapes_are_bitwise_equal(gpu_lib):
 
 def test_batch_member_over_4gib_steps_as_alone(gpu_lib):
     """A member whose buffer takes more than 4 GiB (2048 x 37000 nodes, 4.4 GB
-    per buffer) has its plain rows updated by one-row walked tiles instead of
-    runs, whose byte offsets are 32-bit; it evolves bit for bit as when stepped
-    alone, beside a small member whose rows go to runs."""
+    per buffer: row bases past 32-bit byte offsets) evolves bit for bit as when
+    stepped alone, beside a small member, with one and two waves per row
+    workgroup."""
     import torch
     L = gpu_lib
     big_nx, big_ny = 2048, 37000
