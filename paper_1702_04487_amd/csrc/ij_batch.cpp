@@ -272,7 +272,7 @@ hipError_t one_step(ij_batch* b, int parity, bool diag, bool with_tick, hipStrea
         e = ij::launch_batch_diag(b->d_cases, (int)b->sims.size(), b->max_nx, b->max_ny, b->max_ghost, parity, b->d_t,
                                   b->d_nrec, b->d_active, st);
     if (e == hipSuccess && b->T.n_rows > 0 && b->T.n_gen > 0) {
-        // the row tiles and the general pieces touch disjoint rows: the
+        // the row pieces and the general pieces touch disjoint rows: the
         // latency-bound pieces run on the side stream beside the row launch
         e = hipEventRecord(b->ev_fork, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
