@@ -150,6 +150,70 @@ def test_uniform_states_are_fixed_points(oracle_mod, bc_y, phase):
         assert np.max(np.abs(g1 - g0)) < 1e-14
 
 
+def _box_with_corners(n=40):
+    """A periodic n x n lattice with a closed box (walls two nodes thick, the
+    inner wall class) and an L-shaped obstacle of the outer class inside it:
+    the box's inner corners and the L's inner angle hold solid nodes whose
+    only fluid neighbour is diagonal, so their wetting ghost takes the
+    diagonal rule."""
+    wall = np.zeros((n, n), np.uint8)
+    wall[4:6, 4:36] = wall[34:36, 4:36] = W.WALL_INNER
+    wall[4:36, 4:6] = wall[4:36, 34:36] = W.WALL_INNER
+    wall[12:16, 12:26] = W.WALL_OUTER
+    wall[12:28, 12:16] = W.WALL_OUTER
+    return wall
+
+
+@pytest.mark.parametrize("phase", [1.0, -1.0])
+def test_uniform_phase_with_neutral_walls_is_a_fixed_point(oracle_mod, phase):
+    """With neutral walls (90 degrees: no wetting offset) a uniform bulk phase
+    at rest is an equilibrium beside walls too: every ghost, the diagonal
+    corner rule included, must repeat the bulk phi, and bounce-back must keep
+    the rest state.  A ghost that is not a mean of its fluid neighbours moves
+    the fluid next to the corners."""
+    O = oracle_mod
+    n = 40
+    p = W.base_params(n, n, bc_y=0, tau_ink=0.8, tau_amb=1.3, tau_phi=0.9, theta_inner=90.0,
+                      theta_outer=90.0)
+    s = _sim(O, p, _box_with_corners(n))
+    s.init_phi(np.full((n, n), phase * s.derived()["phi_star"]))
+    f0, g0 = s.get_state()
+    s.step(50)
+    f1, g1 = s.get_state()
+    assert np.max(np.abs(f1 - f0)) < 1e-13
+    assert np.max(np.abs(g1 - g0)) < 1e-13
+
+
+def test_rotation_covariance_with_corner_ghosts(oracle_mod):
+    """D2Q9 and D2Q5 are closed under a quarter turn, and so is the update on
+    a square periodic lattice without body force: turning the walls and the
+    initial drops by 90 degrees turns the state after any number of steps.
+    Drops touch both wall classes (60 and 120 degrees) and the corners where
+    the ghost takes the diagonal rule, so an index slip there (a missing or
+    repeated direction) breaks the symmetry."""
+    O = oracle_mod
+    n = 40
+    p = W.base_params(n, n, bc_y=0, tau_ink=0.7, tau_amb=1.1, tau_phi=0.9, theta_inner=60.0,
+                      theta_outer=120.0)
+    wall = _box_with_corners(n)
+    d = W.discs_distance(n, n, [(9.5, 9.0, 5.0), (29.0, 28.5, 6.0), (20.0, 19.0, 3.5)])
+    a = _sim(O, p, wall)
+    a.init_distance(d)
+    b = _sim(O, p, np.ascontiguousarray(np.rot90(wall, -1)))
+    b.init_distance(np.ascontiguousarray(np.rot90(d, -1)))
+    a.step(150)
+    b.step(150)
+    fa, ga = a.get_state()
+    fb, gb = b.get_state()
+    # a quarter turn maps c_1 -> c_2 -> c_3 -> c_4 -> c_1 and c_5 -> c_6 -> c_7 -> c_8 -> c_5
+    to = [0, 2, 3, 4, 1, 6, 7, 8, 5]
+    assert np.max(np.abs(fa)) > 0.1 and np.max(np.abs(ga[1:])) > 1e-3
+    for i in range(9):
+        assert np.max(np.abs(fb[to[i]] - np.rot90(fa[i], -1))) < 1e-12, i
+    for i in range(5):
+        assert np.max(np.abs(gb[to[i]] - np.rot90(ga[i], -1))) < 1e-12, i
+
+
 def test_stencils_exact_on_quadratics(oracle_mod):
     O = oracle_mod
     nx, ny = 12, 10
