@@ -49,6 +49,20 @@ def _case(name):
         wall[30:33, 5:7] = W.WALL_INNER
         d = W.discs_distance(nx, ny, [(35.0, 12.0, 9.0), (10.0, 36.0, 6.0)])
         return p, wall, d
+    if name == "box_corners":
+        # a closed box (inner wall class) with an L-shaped obstacle (outer
+        # class): solid nodes whose only fluid neighbour is diagonal take the
+        # corner rule of the wetting ghost
+        n = 40
+        p = W.base_params(n, n, bc_y=W.BC_PERIODIC, theta_inner=60.0, theta_outer=120.0, tau_ink=0.7,
+                          tau_amb=1.1, tau_phi=0.9, force_rows=n, f_pos=2e-5, t_pos=10 ** 6)
+        wall = np.zeros((n, n), np.uint8)
+        wall[4:6, 4:36] = wall[34:36, 4:36] = W.WALL_INNER
+        wall[4:36, 4:6] = wall[4:36, 34:36] = W.WALL_INNER
+        wall[12:16, 12:26] = W.WALL_OUTER
+        wall[12:28, 12:16] = W.WALL_OUTER
+        d = W.discs_distance(n, n, [(9.5, 9.0, 5.0), (29.0, 28.5, 6.0), (20.0, 19.0, 3.5)])
+        return p, wall, d
     if name == "narrow_open":
         nx, ny = 3, 50
         p = W.base_params(nx, ny, bc_y=W.BC_OPEN, force_rows=20, f_pos=1e-4, t_pos=10 ** 6)
@@ -57,7 +71,7 @@ def _case(name):
     raise KeyError(name)
 
 
-CASES = ["periodic_drops", "nozzle_ragged", "walls_block", "narrow_open"]
+CASES = ["periodic_drops", "nozzle_ragged", "walls_block", "box_corners", "narrow_open"]
 
 
 def _pair(O, gpu, p, wall, d):
@@ -183,6 +197,19 @@ def test_nozzle_64x256_1000_steps(oracle_mod, gpu_lib):
         for k, v in errs.items():
             worst[k] = max(worst.get(k, 0.0), v)
     print("worst relative L2:", worst)
+
+
+def test_box_corners_300_steps(oracle_mod, gpu_lib):
+    """The closed box with an L-shaped obstacle (corner ghosts of both wall
+    classes) while the drops wet the walls and the body force stirs the box:
+    fields within 1e-5 relative L2 of the FP64 oracle, and every node's n and
+    phi within 1e-5 of n0 and phi*, at steps 100 and 300."""
+    p, wall, d = _case("box_corners")
+    o, g = _pair(oracle_mod, gpu_lib, p, wall, d)
+    for t in (100, 300):
+        o.step(t - o.t)
+        g.step(t - g.t)
+        print(t, _compare_fields(o, g, 1e-5, elementwise=True))
 
 
 def test_diagnostics_match_oracle(oracle_mod, gpu_lib):
