@@ -275,7 +275,8 @@ typedef struct ij_batch ij_batch;
  * On failure *out is NULL and ij_batch_last_error(NULL) has the reason. */
 ij_status ij_batch_create(const ij_params *cases, int32_t n, ij_batch **out);
 
-/* Frees the batch and every case handle (waits for its device work). */
+/* Frees the batch and every case handle, after waiting for all work on the
+ * device (a step without graphs runs on the caller's stream). */
 void ij_batch_destroy(ij_batch *b);
 
 const char *ij_batch_last_error(const ij_batch *b);

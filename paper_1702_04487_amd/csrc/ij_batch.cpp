@@ -469,8 +469,9 @@ ij_status ij_batch_create(const ij_params* cases, int32_t n, ij_batch** out)
 void ij_batch_destroy(ij_batch* b)
 {
     if (!b) return;
-    if (b->cs) (void)hipStreamSynchronize(b->cs);
-    if (b->side) (void)hipStreamSynchronize(b->side);
+    // steps without graphs run on the caller's stream: wait for the whole
+    // device, not only for the batch's own streams, before freeing
+    (void)hipDeviceSynchronize();
     drop_graph(b);
     for (ij_sim* s : b->sims) destroy_sim(s);
     if (b->d_cases) (void)hipFree(b->d_cases);
