@@ -57,7 +57,8 @@ struct ij_batch {
     int64_t* h_nrec = nullptr;
     int* h_active = nullptr;
     hipEvent_t staged = nullptr;   // the uploads of the last call have been read
-    int max_nx = 0, max_ny = 0, max_ghost = 0;
+    int max_nx = 0, max_ny = 0;
+    size_t max_parts = 0;   // sample partials of the widest case, [ceil(nx/64)][ny]
     // graph of graph_steps steps starting at a step that is a multiple of it
     hipStream_t cs = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -167,12 +168,6 @@ ij_status build_tiles(ij_batch* b)
                 }
         for (const int4& g : s->gtiles_host) lists[2].push_back(make_int4((int)c, g.x, g.y | (g.w << 16), g.z));
     }
-    int mg = 0;
-    for (const ij_sim* s : b->sims) mg = std::max(mg, s->n_ghost);
-    if (mg != b->max_ghost) {   // a launch dimension of the diagnostics
-        b->max_ghost = mg;
-        drop_graph(b);
-    }
     std::vector<int4> all;
     for (auto& l : lists) all.insert(all.end(), l.begin(), l.end());
     const int counts[4] = {(int)lists[0].size(), (int)lists[1].size(), (int)lists[2].size(), (int)lists[3].size()};
@@ -236,11 +231,9 @@ ij_status stage(ij_batch* b, hipStream_t st)
         r.buf[1] = s->buf[1 - s->cur];
         r.wall = s->wall;
         r.plain = s->plain;
-        r.phi = s->phi;
-        r.ghost = s->ghost;
+        r.parts = s->sample_parts;
         r.rows = s->rows;
         r.ring = s->samples;
-        r.n_ghost = s->n_ghost;
         r.row0 = (int)s->p.diag_row0;
         r.a_min = (int)std::ceil(4.0 * s->p.width * s->p.width);
         r.band = diag_band(s->p.width);
@@ -268,21 +261,22 @@ ij_status stage(ij_batch* b, hipStream_t st)
 hipError_t one_step(ij_batch* b, int parity, bool diag, bool with_tick, hipStream_t st)
 {
     hipError_t e = hipSuccess;
-    if (diag)
-        e = ij::launch_batch_diag(b->d_cases, (int)b->sims.size(), b->max_nx, b->max_ny, b->max_ghost, parity, b->d_t,
-                                  b->d_nrec, b->d_active, st);
+    if (diag) e = ij::launch_batch_sample_begin(b->d_cases, (int)b->sims.size(), b->max_parts, st);
     if (e == hipSuccess && b->T.n_rows > 0 && b->T.n_gen > 0) {
         // the row pieces and the general pieces touch disjoint rows: the
         // latency-bound pieces run on the side stream beside the row launch
         e = hipEventRecord(b->ev_fork, st);
         if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
-        if (e == hipSuccess) e = ij::launch_batch_general(b->T, b->d_cases, parity, b->d_active, b->waves_x, b->side);
-        if (e == hipSuccess) e = ij::launch_batch_rows(b->T, b->d_cases, parity, b->d_active, b->waves_x, st);
+        if (e == hipSuccess)
+            e = ij::launch_batch_general(b->T, b->d_cases, parity, b->d_active, b->waves_x, diag, b->side);
+        if (e == hipSuccess) e = ij::launch_batch_rows(b->T, b->d_cases, parity, b->d_active, b->waves_x, diag, st);
         if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->side);
         if (e == hipSuccess) e = hipStreamWaitEvent(st, b->ev_join, 0);
     } else if (e == hipSuccess) {
-        e = ij::launch_batch_collide(b->T, b->d_cases, parity, b->d_active, b->waves_x, st);
+        e = ij::launch_batch_collide(b->T, b->d_cases, parity, b->d_active, b->waves_x, diag, st);
     }
+    if (e == hipSuccess && diag)
+        e = ij::launch_batch_sample_end(b->d_cases, (int)b->sims.size(), b->max_ny, b->d_t, b->d_nrec, b->d_active, st);
     if (e == hipSuccess && with_tick)
         e = ij::launch_batch_tick(b->d_t, b->d_cases, (int)b->sims.size(), b->d_active, st);
     return e;
@@ -442,6 +436,14 @@ ij_status ij_batch_create(const ij_params* cases, int32_t n, ij_batch** out)
         b->sims.push_back(s);
         b->max_nx = std::max(b->max_nx, s->nx);
         b->max_ny = std::max(b->max_ny, s->ny);
+        // the partials a sampling step reduces (each case's sample is taken
+        // inside the collide launches)
+        const size_t np = (size_t)((s->nx + 63) / 64) * (size_t)s->ny;
+        b->max_parts = std::max(b->max_parts, np);
+        if (hipMalloc(&s->sample_parts, np * sizeof(ij::DiagRow)) != hipSuccess) {
+            s->sample_parts = nullptr;
+            return cleanup(IJ_ERR_OOM, "case " + std::to_string(c) + ": sample partials allocation failed");
+        }
     }
     const size_t nb = (size_t)n;
     if (hipMalloc(&b->d_cases, nb * sizeof(ij::CaseRec)) != hipSuccess ||

@@ -55,11 +55,10 @@ struct CaseRec {
     float* buf[2];          // distribution buffers; buf[0] holds the state at parity 0
     const uint8_t* wall;    // [ny][pitch]
     const uint8_t* plain;   // plain-row table [n_strips][ny]
-    double* phi;            // phi~ field of the diagnostics [ny][pitch]
-    const int2* ghost;      // solid nodes that touch fluid
+    DiagRow* parts;         // sample partials [ceil(nx/64)][ny] of a sampling step
     DiagRow* rows;          // [ny]
     SampleRec* ring;        // diagnostics records
-    int n_ghost, row0, a_min, band;
+    int row0, a_min, band;
     int64_t t_pos, t_neg, t_idle;
     int periodic;
     double f_pos, f_neg, u_limit;
@@ -114,21 +113,29 @@ struct BatchTiles {
     int n_wide, n_tail, n_gen, n_rows;
     int grid_wide, grid_tail;
 };
+// With sample, the step also takes each case's diagnostics sample of its
+// input state into the case's partials (cleared before by
+// launch_batch_sample_begin, reduced after by launch_batch_sample_end).
 hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
-                                int waves_x, hipStream_t st);
-// the two halves of launch_batch_collide: the row tiles of the plain rows,
+                                int waves_x, bool sample, hipStream_t st);
+// the two halves of launch_batch_collide: the row pieces of the plain rows,
 // and the rest (walked plain tiles, general pieces); independent of each
 // other within a step
 hipError_t launch_batch_rows(const BatchTiles& T, const CaseRec* cases, int parity, const int* active, int waves_x,
-                             hipStream_t st);
+                             bool sample, hipStream_t st);
 hipError_t launch_batch_general(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
-                                int waves_x, hipStream_t st);
+                                int waves_x, bool sample, hipStream_t st);
 // advances the step counter; a case switched off has its two buffers swapped,
 // so that the buffer a step reads is always the one that holds its state
 hipError_t launch_batch_tick(int64_t* t_dev, CaseRec* cases, int n_cases, const int* active, hipStream_t st);
 hipError_t launch_batch_set_time(int64_t* t_dev, int64_t t, CaseRec* cases, int n_cases, hipStream_t st);
-hipError_t launch_batch_diag(const CaseRec* cases, int n_cases, int max_nx, int max_ny, int max_ghost, int parity,
-                             const int64_t* t_dev, int64_t* n_rec, int* active, hipStream_t st);
+// A sampling step: clear every case's partials (max_parts: the most any case
+// has), step with sample set, then sum each active case's partials per row
+// and reduce them to the record at n_rec[case] of its ring; a record that
+// fails the guard switches its case off.
+hipError_t launch_batch_sample_begin(const CaseRec* cases, int n_cases, size_t max_parts, hipStream_t st);
+hipError_t launch_batch_sample_end(const CaseRec* cases, int n_cases, int max_ny, const int64_t* t_dev, int64_t* n_rec,
+                                   int* active, hipStream_t st);
 // workgroups of the plain batched kernel that are resident at once on the
 // current device (0 on error)
 int batch_resident_workgroups(int waves_x);

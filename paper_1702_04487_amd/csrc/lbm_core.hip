@@ -1544,7 +1544,7 @@ __device__ __forceinline__ double case_pulse(const CaseRec& c, int64_t t)
 // cache); a launch takes the tiles of its own width (64 * NW columns).  With
 // one tile per workgroup, odd row blocks walk down, as in the single-lattice
 // launch (consecutive workgroups then meet in their shared halo rows).
-template <int NW, bool PLAIN>
+template <int NW, bool PLAIN, bool SAMPLE = false>
 __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __restrict__ cases,
                                                            const int4* __restrict__ tiles, int n_tiles,
                                                            int per_wg, int parity, const int* __restrict__ active)
@@ -1558,8 +1558,8 @@ __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __rest
         const KParams P = R.P;   // P.fb: the case's body force of this step
         const int y0 = tl.z & 0xffff;
         const bool down = single && ((tl.z >> 30) & 1);
-        collide_tile<NW, PLAIN>(P, P.fb, R.buf[parity], R.buf[1 - parity], R.wall, R.plain, tl.y, tl.w, y0,
-                                y0 + ((tl.z >> 16) & 0x3fff), nullptr, down);
+        collide_tile<NW, PLAIN, SAMPLE>(P, P.fb, R.buf[parity], R.buf[1 - parity], R.wall, R.plain, tl.y, tl.w,
+                                        y0, y0 + ((tl.z >> 16) & 0x3fff), SAMPLE ? R.parts : nullptr, down);
     }
 }
 
@@ -1568,7 +1568,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_collide(const CaseRec* __rest
 // collide_row_wave), listed case by case, row-major: workgroup g takes pieces
 // NW g .. NW g + NW - 1, and XCD x (workgroup b % 8) takes the x-th contiguous
 // range of workgroups, so that neighbouring rows of a case share one L2.
-template <int NW>
+template <int NW, bool SAMPLE>
 __global__ __launch_bounds__(64 * NW) void k_batch_rows(const CaseRec* __restrict__ cases,
                                                         const int4* __restrict__ pieces, int n_pieces, int parity,
                                                         const int* __restrict__ active)
@@ -1582,7 +1582,7 @@ __global__ __launch_bounds__(64 * NW) void k_batch_rows(const CaseRec* __restric
     // the guard flag is read with the record: one round trip before the populations
     if (!active[r.x]) return;
     const KParams P = R.P;   // P.fb: the case's body force of this step
-    collide_row_wave<false, true>(P, P.fb, R.buf[parity], R.buf[1 - parity], r.y, r.z, nullptr);
+    collide_row_wave<SAMPLE, true>(P, P.fb, R.buf[parity], R.buf[1 - parity], r.y, r.z, SAMPLE ? R.parts : nullptr);
 }
 
 // One workgroup: the step counter moves on, a case the guard froze swaps
@@ -1612,30 +1612,31 @@ __global__ __launch_bounds__(1024) void k_batch_set_time(int64_t* t_dev, int64_t
     for (int c = threadIdx.x; c < n_cases; c += blockDim.x) cases[c].P.fb = (float)case_pulse(cases[c], t);
 }
 
-__global__ void k_batch_phi(const CaseRec* __restrict__ cases, int parity)
-{
-    const CaseRec& R = cases[blockIdx.z];
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y;
-    if (x < R.P.nx && y < R.P.ny) phi_node(R.P, R.buf[parity], R.wall, R.phi, x, y);
-}
-
-// grid (blocks of 256 ghost nodes, case)
-__global__ void k_batch_ghost(const CaseRec* __restrict__ cases)
+// A sampling step takes each case's sample of its input state inside the
+// collide launches (per 64-column piece and row, as the single-lattice step
+// does).  Grid (pieces / 256, case): the partials are cleared first.
+__global__ void k_batch_sample_clear(const CaseRec* __restrict__ cases)
 {
     const CaseRec& R = cases[blockIdx.y];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < R.n_ghost) ghost_node(R.P, R.ghost[i], R.wall, R.phi);
+    const size_t n = (size_t)((R.P.nx + 63) / 64) * R.P.ny;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) R.parts[i] = DiagRow{};
 }
 
-// grid (row, case)
-__global__ __launch_bounds__(DIAG_THREADS) void k_batch_diag_rows(const CaseRec* __restrict__ cases, int parity,
-                                                                 const int64_t* __restrict__ t_dev)
+// grid (rows / 256, case): rows[y] = the partials of row y summed over the
+// pieces in order.  A case the guard switched off keeps the rows of its
+// failing sample (its state has not changed since), so its later records
+// repeat that sample.
+__global__ void k_batch_sample_rows(const CaseRec* __restrict__ cases, const int* __restrict__ active)
 {
-    const CaseRec& R = cases[blockIdx.y];
-    if ((int)blockIdx.x >= R.P.ny) return;
-    const KParams P = R.P;
-    diag_row(P, (float)case_pulse(R, *t_dev), R.buf[parity], R.wall, R.phi, R.row0, R.rows, blockIdx.x);
+    const int c = blockIdx.y;
+    const CaseRec& R = cases[c];
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (!active[c] || y >= R.P.ny) return;
+    const int n_sub = (R.P.nx + 63) / 64;
+    DiagRow r{};
+    for (int k = 0; k < n_sub; ++k) sample_add(r, R.parts[(size_t)k * R.P.ny + y]);
+    R.rows[y] = r;
 }
 
 // grid (case): the sample goes to the case's ring at n_rec[case], which is
@@ -1800,22 +1801,23 @@ int batch_resident_workgroups(int waves_x)
     return e == hipSuccess ? cus * per_cu : 0;
 }
 
-hipError_t launch_batch_rows(const BatchTiles& T, const CaseRec* cases, int parity, const int* active, int waves_x,
-                             hipStream_t st)
+template <bool S>
+static hipError_t launch_batch_rows_t(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
+                                      int waves_x, hipStream_t st)
 {
-    if (parity & ~1) return hipErrorInvalidValue;
     if (T.n_rows > 0) {   // pieces: one per wave
         const unsigned n = (unsigned)T.n_rows;
         switch (waves_x) {
         case 1:
-            hipLaunchKernelGGL((k_batch_rows<1>), dim3(n), dim3(64), 0, st, cases, T.rows, T.n_rows, parity, active);
+            hipLaunchKernelGGL((k_batch_rows<1, S>), dim3(n), dim3(64), 0, st, cases, T.rows, T.n_rows, parity,
+                               active);
             break;
         case 2:
-            hipLaunchKernelGGL((k_batch_rows<2>), dim3((n + 1) / 2), dim3(128), 0, st, cases, T.rows, T.n_rows,
+            hipLaunchKernelGGL((k_batch_rows<2, S>), dim3((n + 1) / 2), dim3(128), 0, st, cases, T.rows, T.n_rows,
                                parity, active);
             break;
         case 4:
-            hipLaunchKernelGGL((k_batch_rows<4>), dim3((n + 3) / 4), dim3(256), 0, st, cases, T.rows, T.n_rows,
+            hipLaunchKernelGGL((k_batch_rows<4, S>), dim3((n + 3) / 4), dim3(256), 0, st, cases, T.rows, T.n_rows,
                                parity, active);
             break;
         default:
@@ -1825,12 +1827,20 @@ hipError_t launch_batch_rows(const BatchTiles& T, const CaseRec* cases, int pari
     return hipGetLastError();
 }
 
-// the walked plain tiles (one launch per strip width; persistent when the
-// grid is smaller than the tile count), then the general pieces
-hipError_t launch_batch_general(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
-                                int waves_x, hipStream_t st)
+hipError_t launch_batch_rows(const BatchTiles& T, const CaseRec* cases, int parity, const int* active, int waves_x,
+                             bool sample, hipStream_t st)
 {
     if (parity & ~1) return hipErrorInvalidValue;
+    return sample ? launch_batch_rows_t<true>(T, cases, parity, active, waves_x, st)
+                  : launch_batch_rows_t<false>(T, cases, parity, active, waves_x, st);
+}
+
+// the walked plain tiles (one launch per strip width; persistent when the
+// grid is smaller than the tile count), then the general pieces
+template <bool S>
+static hipError_t launch_batch_general_t(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
+                                         int waves_x, hipStream_t st)
+{
     auto runs = [&](int n, int grid, int& per_wg) {
         grid = n > 0 ? std::min(grid, n) : 0;
         per_wg = grid > 0 ? (n + grid - 1) / grid : 0;
@@ -1840,20 +1850,20 @@ hipError_t launch_batch_general(const BatchTiles& T, const CaseRec* cases, int p
     const int gw = runs(T.n_wide, T.grid_wide, pw);
     const int gt = runs(T.n_tail, T.grid_tail, pt);
     if (gt > 0)
-        hipLaunchKernelGGL((k_batch_collide<1, true>), dim3(gt), dim3(64), 0, st, cases, T.tail, T.n_tail, pt,
+        hipLaunchKernelGGL((k_batch_collide<1, true, S>), dim3(gt), dim3(64), 0, st, cases, T.tail, T.n_tail, pt,
                            parity, active);
     if (gw > 0) {
         switch (waves_x) {
         case 1:
-            hipLaunchKernelGGL((k_batch_collide<1, true>), dim3(gw), dim3(64), 0, st, cases, T.wide, T.n_wide, pw,
+            hipLaunchKernelGGL((k_batch_collide<1, true, S>), dim3(gw), dim3(64), 0, st, cases, T.wide, T.n_wide, pw,
                                parity, active);
             break;
         case 2:
-            hipLaunchKernelGGL((k_batch_collide<2, true>), dim3(gw), dim3(128), 0, st, cases, T.wide, T.n_wide, pw,
+            hipLaunchKernelGGL((k_batch_collide<2, true, S>), dim3(gw), dim3(128), 0, st, cases, T.wide, T.n_wide, pw,
                                parity, active);
             break;
         case 4:
-            hipLaunchKernelGGL((k_batch_collide<4, true>), dim3(gw), dim3(256), 0, st, cases, T.wide, T.n_wide, pw,
+            hipLaunchKernelGGL((k_batch_collide<4, true, S>), dim3(gw), dim3(256), 0, st, cases, T.wide, T.n_wide, pw,
                                parity, active);
             break;
         default:
@@ -1861,16 +1871,24 @@ hipError_t launch_batch_general(const BatchTiles& T, const CaseRec* cases, int p
         }
     }
     if (T.n_gen > 0)
-        hipLaunchKernelGGL((k_batch_collide<1, false>), dim3(T.n_gen), dim3(64), 0, st, cases, T.gen, T.n_gen, 1,
+        hipLaunchKernelGGL((k_batch_collide<1, false, S>), dim3(T.n_gen), dim3(64), 0, st, cases, T.gen, T.n_gen, 1,
                            parity, active);
     return hipGetLastError();
 }
 
-hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
-                                int waves_x, hipStream_t st)
+hipError_t launch_batch_general(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
+                                int waves_x, bool sample, hipStream_t st)
 {
-    const hipError_t e = launch_batch_rows(T, cases, parity, active, waves_x, st);
-    return e != hipSuccess ? e : launch_batch_general(T, cases, parity, active, waves_x, st);
+    if (parity & ~1) return hipErrorInvalidValue;
+    return sample ? launch_batch_general_t<true>(T, cases, parity, active, waves_x, st)
+                  : launch_batch_general_t<false>(T, cases, parity, active, waves_x, st);
+}
+
+hipError_t launch_batch_collide(const BatchTiles& T, const CaseRec* cases, int parity, const int* active,
+                                int waves_x, bool sample, hipStream_t st)
+{
+    const hipError_t e = launch_batch_rows(T, cases, parity, active, waves_x, sample, st);
+    return e != hipSuccess ? e : launch_batch_general(T, cases, parity, active, waves_x, sample, st);
 }
 
 hipError_t launch_batch_tick(int64_t* t_dev, CaseRec* cases, int n_cases, const int* active, hipStream_t st)
@@ -1885,15 +1903,21 @@ hipError_t launch_batch_set_time(int64_t* t_dev, int64_t t, CaseRec* cases, int 
     return hipGetLastError();
 }
 
-hipError_t launch_batch_diag(const CaseRec* cases, int n_cases, int max_nx, int max_ny, int max_ghost, int parity,
-                             const int64_t* t_dev, int64_t* n_rec, int* active, hipStream_t st)
+hipError_t launch_batch_sample_begin(const CaseRec* cases, int n_cases, size_t max_parts, hipStream_t st)
 {
     if (n_cases <= 0) return hipSuccess;
-    if (n_cases > 65535 || max_ny > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_batch_phi, dim3((max_nx + 255) / 256, max_ny, n_cases), dim3(256), 0, st, cases, parity);
-    if (max_ghost > 0)
-        hipLaunchKernelGGL(k_batch_ghost, dim3((max_ghost + 255) / 256, n_cases), dim3(256), 0, st, cases);
-    hipLaunchKernelGGL(k_batch_diag_rows, dim3(max_ny, n_cases), dim3(DIAG_THREADS), 0, st, cases, parity, t_dev);
+    if (n_cases > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_sample_clear, dim3((unsigned)((max_parts + 255) / 256), n_cases), dim3(256), 0, st,
+                       cases);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sample_end(const CaseRec* cases, int n_cases, int max_ny, const int64_t* t_dev, int64_t* n_rec,
+                                   int* active, hipStream_t st)
+{
+    if (n_cases <= 0) return hipSuccess;
+    if (n_cases > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_batch_sample_rows, dim3((max_ny + 255) / 256, n_cases), dim3(256), 0, st, cases, active);
     hipLaunchKernelGGL(k_batch_diag_finish, dim3(n_cases), dim3(DIAG_THREADS), 0, st, cases, t_dev, n_rec, active);
     return hipGetLastError();
 }
