@@ -188,6 +188,10 @@ def test_batch_unstable_case_is_frozen_and_flagged(gpu_lib):
         assert _same(b.cases[1], ref), extra
     smp = [x for x in b.cases[1].samples() if x["step"] >= tf]
     assert len(smp) > 3 and all(x["mass_n"] == smp[0]["mass_n"] for x in smp)
+    # every later record repeats the failing sample (the state has not moved), field by field
+    same = lambda u, v: u == v or (u != u and v != v)   # noqa: E731  (NaN equals NaN here)
+    for x in smp[1:]:
+        assert all(same(x[k], smp[0][k]) for k in smp[0] if k != "step"), (x, smp[0])
     b.close()
 
 
